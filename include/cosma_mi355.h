@@ -1,0 +1,200 @@
+/*
+ * cosma_mi355 -- dense C = alpha*A*B + beta*C on one MI355X (gfx950), run
+ * under the I/O-optimal schedule of Kwasniewski et al., "Red-Blue Pebbling
+ * Revisited: Near Optimal Parallel Matrix-Matrix Multiplication" (SC'19).
+ *
+ * The product computed is the classical one of section 2.4 (A is m x k,
+ * B is k x n, C is m x n), entry by entry the sum over the reduction index
+ * of the CDAG update rule of section 4.1; only the order of that sum differs
+ * between schedules.  Algorithm 1 gives the structure of every call: pick the
+ * sequential schedule (section 5), parallelise it (eq. optTileShape,
+ * section 6.3), fit it to the processors (section 7.1), stream the
+ * reduction dimension in rounds (the DistrData / Multiply loop) and reduce
+ * partial results when k is split (Reduce).  Here a "processor" is a
+ * compute unit and its fast memory S is the CU's register file plus LDS.
+ *
+ * Conventions shared by every entry point
+ *  - Row-major, no transposes.  A: m x k, lda >= max(1,k).  B: k x n,
+ *    ldb >= max(1,n).  C: m x n, ldc >= max(1,n).
+ *  - A, B, C and any workspace are device pointers owned by the caller; the
+ *    library never frees or retains caller memory beyond the call, except
+ *    the workspace registered with cosma_set_workspace (borrowed until
+ *    replaced) and batch handles (see cosma_batch_create).
+ *  - alpha and beta are host doubles; FP32-class dtypes round them to fp32.
+ *  - BLAS rules: m == 0 or n == 0 is a no-op; k == 0 or alpha == 0 gives
+ *    C = beta*C without reading A or B; beta == 0 never reads C (NaNs in C
+ *    are overwritten).
+ *  - Every GPU entry point is asynchronous on `stream` (a hipStream_t, or
+ *    NULL for the default stream) and returns once the work is enqueued.
+ *  - Errors are returned as negative cosma_status values; on an argument
+ *    error nothing is enqueued.  No entry point allocates device memory on
+ *    the compute path; partial results live in the caller's workspace.
+ *  - Calls that share the registered workspace must be ordered on one
+ *    stream (or synchronised by the caller).
+ */
+#ifndef COSMA_MI355_H
+#define COSMA_MI355_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define COSMA_API __attribute__((visibility("default")))
+#else
+#define COSMA_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  COSMA_F64 = 0,          /* binary64 operands and result, FP64 MFMA */
+  COSMA_F32 = 1,          /* binary32 operands and result, FP32 MFMA */
+  COSMA_F32_BF16X3 = 2,   /* binary32 operands and result; each operand split
+                             into bf16 hi + lo, three bf16 MFMA products,
+                             fp32 accumulation */
+  COSMA_F64_OZAKI_I8 = 3  /* binary64 operands and result; operands split into
+                             int8 digit slices, exact int32 MFMA products,
+                             binary64 summation */
+} cosma_dtype;
+
+typedef enum {
+  COSMA_OK = 0,
+  COSMA_ERR_INVALID_ARG = -1, /* bad size, leading dimension, pointer, dtype or plan */
+  COSMA_ERR_HIP = -2,         /* a HIP runtime call failed */
+  COSMA_ERR_WORKSPACE = -3,   /* the plan needs more workspace than is registered */
+  COSMA_ERR_UNSUPPORTED = -4, /* no device, wrong architecture, or unsupported case */
+  COSMA_ERR_NO_MEMORY = -5    /* host allocation failed (planner / batch metadata) */
+} cosma_status;
+
+/* Hardware figures the planner uses (queried from the device, or defaults
+   for MI355X when no device is present). */
+typedef struct {
+  int32_t num_cus;            /* compute units ("processors") */
+  int32_t num_xcds;           /* accelerator dies; each has its own L2 */
+  int64_t lds_bytes_per_cu;   /* local data share per CU */
+  int64_t vgpr_bytes_per_cu;  /* vector register file (arch + acc) per CU */
+  int64_t l2_bytes_per_xcd;   /* L2 per XCD */
+  double clock_ghz;           /* peak engine clock */
+  double hbm_gbps;            /* peak HBM bandwidth, GB/s */
+} cosma_device_facts;
+
+/* A schedule for one product, as chosen by the planner (Algorithm 1's
+   FindSeqSchedule / ParallelizeSched / FitRanks mapped onto the CUs). */
+typedef struct {
+  int64_t m, n, k;
+  int32_t dtype;              /* cosma_dtype */
+  int32_t tile_id;            /* index into the dtype's kernel tile menu */
+  int32_t tile_m, tile_n;     /* C block per work item (the paper's a x a face) */
+  int32_t tile_k;             /* reduction rounds: k-panel depth per LDS stage */
+  int32_t p_m, p_n, p_k;      /* grid: row blocks, column blocks, k splits */
+  int32_t group_m;            /* raster group height (tile rows per group) */
+  int32_t wg_per_cu;          /* resident work items per CU */
+  int32_t regime;             /* 0: ij-parallel (p <= p1), 1: k is cut (p > p1) */
+  int32_t slices;             /* Ozaki digit slices per operand (0 otherwise) */
+  int64_t k_split;            /* reduction length per split (multiple of tile_k) */
+  int64_t items;              /* p_m * p_n * p_k */
+  int64_t waves;              /* ceil(items / resident slots) */
+  double S_words;             /* per-CU fast memory in words of the operand type */
+  double p1;                  /* mn / S: dependency-free sqrt(S) x sqrt(S) x k domains */
+  int64_t a_seq, b_seq;       /* integer optimum of section 5 for S_words */
+  double a_par, b_par;        /* eq. optTileShape with p = num_cus */
+  double q_cu_words;          /* I/O counted at the CU level, in words */
+  double q_ea_bytes;          /* predicted L2 <-> memory bytes for the raster */
+  double thm1_words;          /* Theorem 1 bound 2mnk/sqrt(S) + mn, words */
+  double thm2_words;          /* Theorem 2 bound per CU, words */
+  double predicted_ms;        /* planner time model */
+  size_t workspace_bytes;     /* device workspace the plan needs */
+} cosma_plan_info;
+
+/* ---- single product ---------------------------------------------------- */
+
+/* C = alpha*A*B + beta*C under the planner's schedule (Algorithm 1). */
+COSMA_API int cosma_gemm(int64_t m, int64_t n, int64_t k, double alpha, const void* A, int64_t lda,
+               const void* B, int64_t ldb, double beta, void* C, int64_t ldc, int dtype,
+               void* stream);
+
+/* Same product under an explicit plan (from cosma_plan_query or
+   cosma_plan_make, m/n/k/dtype must match). */
+COSMA_API int cosma_gemm_planned(const cosma_plan_info* plan, double alpha, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
+                       void* stream);
+
+/* ---- batches of independent products (Algorithm 1's "for all p_i in
+   parallel" over many small problems) ------------------------------------ */
+
+/* Variable-size batch: problem i is C_i = alpha_i*A_i*B_i + beta_i*C_i.  All
+   host arrays have length `count` and are read during the call only; the
+   batch runs as one persistent launch (the problems must not alias each
+   other's C).  Supported dtypes: COSMA_F32, COSMA_F64. */
+COSMA_API int cosma_gemm_batched(int64_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+                       const double* alpha, const void* const* A, const int64_t* lda,
+                       const void* const* B, const int64_t* ldb, const double* beta,
+                       void* const* C, const int64_t* ldc, int dtype, void* stream);
+
+/* Capture-once / replay-many batch: plans every problem, uploads the work
+   list and captures the launch into a HIP graph.  The handle owns its device
+   work list and graph until cosma_batch_destroy.  Pointers and sizes are
+   fixed at creation; replays read the current contents of A, B and C. */
+COSMA_API int cosma_batch_create(int64_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+                       const double* alpha, const void* const* A, const int64_t* lda,
+                       const void* const* B, const int64_t* ldb, const double* beta,
+                       void* const* C, const int64_t* ldc, int dtype, void* stream,
+                       void** handle);
+COSMA_API int cosma_batch_run(void* handle, void* stream);
+COSMA_API int cosma_batch_destroy(void* handle);
+
+/* ---- planner (host only; no GPU needed) --------------------------------- */
+
+/* Plan for the current device (MI355X defaults without a device). */
+COSMA_API int cosma_plan_query(int64_t m, int64_t n, int64_t k, int dtype, cosma_plan_info* out);
+/* Plan for given hardware figures and idle budget delta (section 7.1's
+   tunable: the fraction of compute time the planner may give up for less
+   I/O).  facts == NULL means the current device. */
+COSMA_API int cosma_plan_query_facts(int64_t m, int64_t n, int64_t k, int dtype,
+                           const cosma_device_facts* facts, double delta, cosma_plan_info* out);
+/* Plan with a forced tile (menu index) and split factor p_k >= 1. */
+COSMA_API int cosma_plan_make(int64_t m, int64_t n, int64_t k, int dtype, int tile_id, int p_k,
+                    cosma_plan_info* out);
+/* Number of kernel tiles for dtype, and the shape of tile `id`. */
+COSMA_API int cosma_tile_count(int dtype);
+COSMA_API int cosma_tile_shape(int dtype, int id, int32_t* tile_m, int32_t* tile_n, int32_t* tile_k);
+/* Facts of the current device (or the MI355X defaults). */
+COSMA_API int cosma_device_query(cosma_device_facts* out);
+
+/* Theorem 1: 2mnk/sqrt(S) + mn words. */
+COSMA_API double cosma_thm1_bound(double m, double n, double k, double S);
+/* Section 5: integer optimum of max ab/(a+b) s.t. ab + a + 1 <= S. */
+COSMA_API int cosma_seq_schedule(int64_t S, int64_t* a, int64_t* b);
+/* eq. optTileShape: a = min{sqrt S, (mnk/p)^(1/3)}, b = max{mnk/(pS), (mnk/p)^(1/3)}. */
+COSMA_API int cosma_par_schedule(double m, double n, double k, double p, double S, double* a, double* b);
+/* Section 7.1 grid fitting over p' in [ceil((1-delta)p), p] minimising the
+   local-domain surface; grid = (p_m, p_n, p_k), *used = p_m*p_n*p_k. */
+COSMA_API int cosma_fit_ranks(int64_t m, int64_t n, int64_t k, int64_t p, double delta, int64_t grid[3],
+                    int64_t* used);
+/* Words moved by the tiled schedule: k-rounds loading tile_m x kc of A and
+   kc x tile_n of B per work item, C block resident, p_k splits with a
+   partial store + reload when p_k > 1, C0 loads when beta != 0. */
+COSMA_API double cosma_io_count(int64_t m, int64_t n, int64_t k, int64_t tile_m, int64_t tile_n,
+                      int64_t kc, int64_t p_k, int beta_nonzero);
+
+/* ---- workspace ---------------------------------------------------------- */
+
+/* Bytes of workspace the planner's schedule for this product needs. */
+COSMA_API int cosma_workspace_size(int64_t m, int64_t n, int64_t k, int dtype, size_t* bytes);
+/* Register a caller-owned device buffer as the workspace of the current
+   device (ptr == NULL, bytes == 0 unregisters).  The library borrows it
+   until it is replaced; `stream` is unused and reserved. */
+COSMA_API int cosma_set_workspace(void* device_ptr, size_t bytes, void* stream);
+
+/* ---- misc --------------------------------------------------------------- */
+COSMA_API const char* cosma_status_string(int status);
+/* Library version string. */
+COSMA_API const char* cosma_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COSMA_MI355_H */

@@ -1,0 +1,382 @@
+// C ABI of the library: argument checks, the plan cache, the workspace
+// registry and launch sequencing.  See include/cosma_mi355.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/cosma_mi355.h"
+#include "kernels.hpp"
+#include "ozaki.hpp"
+#include "planner.hpp"
+#include "runtime.hpp"
+
+namespace cosma {
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct DeviceState {
+  bool queried = false;
+  int status = COSMA_OK;  // COSMA_ERR_UNSUPPORTED when not gfx950
+  cosma_device_facts facts{};
+  void* workspace = nullptr;
+  size_t workspace_bytes = 0;
+};
+
+std::mutex g_mutex;
+DeviceState g_dev[kMaxDevices];
+std::map<std::tuple<int, int64_t, int64_t, int64_t, int>, cosma_plan_info> g_plans;
+
+double env_delta() {
+  static double d = [] {
+    const char* e = std::getenv("COSMA_DELTA");
+    double v = e ? std::atof(e) : 0.03;
+    return (v >= 0.0 && v < 1.0) ? v : 0.03;
+  }();
+  return d;
+}
+
+}  // namespace
+
+// Current device index, or -1 without a usable device.
+int current_device() {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return -1;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return -1;
+  return dev;
+}
+
+// Facts of the current device (MI355X defaults when there is none).
+// *status: COSMA_OK, or COSMA_ERR_UNSUPPORTED for a device that is not gfx950.
+cosma_device_facts device_facts(int* status) {
+  const int dev = current_device();
+  if (dev < 0) {
+    if (status) *status = COSMA_ERR_UNSUPPORTED;
+    return mi355x_defaults();
+  }
+  std::lock_guard<std::mutex> lock(g_mutex);
+  DeviceState& d = g_dev[dev];
+  if (!d.queried) {
+    d.facts = mi355x_defaults();
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+      if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) d.status = COSMA_ERR_UNSUPPORTED;
+      if (prop.multiProcessorCount > 0) d.facts.num_cus = prop.multiProcessorCount;
+      if (prop.maxSharedMemoryPerMultiProcessor > 0)
+        d.facts.lds_bytes_per_cu = (int64_t)prop.maxSharedMemoryPerMultiProcessor;
+      if (prop.clockRate > 0) d.facts.clock_ghz = prop.clockRate * 1e-6;
+    } else {
+      d.status = COSMA_ERR_HIP;
+    }
+    d.queried = true;
+  }
+  if (status) *status = d.status;
+  return d.facts;
+}
+
+bool workspace_for_current(void** ptr, size_t* bytes) {
+  const int dev = current_device();
+  if (dev < 0) return false;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  *ptr = g_dev[dev].workspace;
+  *bytes = g_dev[dev].workspace_bytes;
+  return true;
+}
+
+int plan_cached(int64_t m, int64_t n, int64_t k, int dtype, cosma_plan_info* out) {
+  const int dev = current_device();
+  int st = COSMA_OK;
+  const cosma_device_facts f = device_facts(&st);
+  const auto key = std::make_tuple(dev, m, n, k, dtype);
+  {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+      *out = it->second;
+      return COSMA_OK;
+    }
+  }
+  const int rc = make_plan(m, n, k, dtype, f, env_delta(), -1, -1, out);
+  if (rc != COSMA_OK) return rc;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  if (g_plans.size() > 4096) g_plans.clear();
+  g_plans[key] = *out;
+  return COSMA_OK;
+}
+
+int map_hip(hipError_t e) { return e == hipSuccess ? COSMA_OK : COSMA_ERR_HIP; }
+
+namespace {
+
+bool aligned_to(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// Argument rules of the header; nothing is launched when this fails.
+int check_args(int64_t m, int64_t n, int64_t k, double alpha, const void* A, int64_t lda,
+               const void* B, int64_t ldb, double beta, const void* C, int64_t ldc, int dtype) {
+  if (dtype < 0 || dtype >= NUM_DTYPES) return COSMA_ERR_INVALID_ARG;
+  if (m < 0 || n < 0 || k < 0) return COSMA_ERR_INVALID_ARG;
+  if (lda < (k > 1 ? k : 1) || ldb < (n > 1 ? n : 1) || ldc < (n > 1 ? n : 1))
+    return COSMA_ERR_INVALID_ARG;
+  const size_t el = (size_t)word_bytes(dtype);
+  if (m == 0 || n == 0) return COSMA_OK;
+  if (!C || !aligned_to(C, el)) return COSMA_ERR_INVALID_ARG;
+  // int64 extents must not overflow
+  const double lim = 9.0e18;
+  if ((double)m * (double)ldc > lim) return COSMA_ERR_INVALID_ARG;
+  if (k > 0 && alpha != 0.0) {
+    if (!A || !B || !aligned_to(A, el) || !aligned_to(B, el)) return COSMA_ERR_INVALID_ARG;
+    if ((double)m * (double)lda > lim || (double)k * (double)ldb > lim) return COSMA_ERR_INVALID_ARG;
+  }
+  (void)beta;
+  return COSMA_OK;
+}
+
+}  // namespace
+
+// Run one product under `plan` (validated by the caller).
+int run_plan(const cosma_plan_info& plan, double alpha, const void* A, int64_t lda, const void* B,
+             int64_t ldb, double beta, void* C, int64_t ldc, hipStream_t stream) {
+  const int64_t m = plan.m, n = plan.n, k = plan.k;
+  const int dtype = plan.dtype;
+  if (m == 0 || n == 0) return COSMA_OK;
+  const bool fp32 = dtype == F32 || dtype == F32_BF16X3;
+  if (k == 0 || alpha == 0.0) {
+    if (fp32) return map_hip(launch_scale_f32((float*)C, ldc, m, n, (float)beta, stream));
+    return map_hip(launch_scale_f64((double*)C, ldc, m, n, beta, stream));
+  }
+  // The requirement is recomputed from the plan's shape, never taken from
+  // its (caller-writable) workspace_bytes field.
+  const size_t need = workspace_bytes(plan);
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  if (need > 0) {
+    if (!workspace_for_current(&ws, &ws_bytes) || ws_bytes < need || !ws)
+      return COSMA_ERR_WORKSPACE;
+  }
+  if (dtype == F64_OZAKI_I8) return run_ozaki(plan, alpha, A, lda, B, ldb, beta, C, ldc, ws, stream);
+
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.m = m;
+  g.n = n;
+  g.k = k;
+  g.k_split = plan.k_split;
+  g.tiles_m = plan.p_m;
+  g.tiles_n = plan.p_n;
+  g.splits = plan.p_k;
+  g.ldp = n;
+  g.split_stride = m * n;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.group_m = plan.group_m > 0 ? plan.group_m : 1;
+  int st = COSMA_OK;
+  g.num_xcds = device_facts(&st).num_xcds;
+  const size_t el = (size_t)word_bytes(dtype);
+  g.vec_a = ((uintptr_t)A % (2 * el) == 0 && lda % 2 == 0) ? 1 : 0;
+  g.vec_b = ((uintptr_t)B % (2 * el) == 0 && ldb % 2 == 0) ? 1 : 0;
+  if (plan.p_k > 1) g.P = ws;
+
+  hipError_t e;
+  switch (dtype) {
+    case F64: e = launch_gemm_f64(plan.tile_id, g, stream); break;
+    case F32: e = launch_gemm_f32(plan.tile_id, g, stream); break;
+    case F32_BF16X3: e = launch_gemm_bf16x3(plan.tile_id, g, stream); break;
+    default: return COSMA_ERR_INVALID_ARG;
+  }
+  if (e != hipSuccess) return COSMA_ERR_HIP;
+  if (plan.p_k > 1) {
+    if (fp32)
+      e = launch_splitk_reduce_f32((const float*)ws, m * n, n, plan.p_k, (float*)C, ldc, m, n,
+                                   (float)alpha, (float)beta, stream);
+    else
+      e = launch_splitk_reduce_f64((const double*)ws, m * n, n, plan.p_k, (double*)C, ldc, m, n,
+                                   alpha, beta, stream);
+    if (e != hipSuccess) return COSMA_ERR_HIP;
+  }
+  return COSMA_OK;
+}
+
+int check_plan(const cosma_plan_info* p) {
+  if (!p) return COSMA_ERR_INVALID_ARG;
+  int cnt = 0;
+  const TileDesc* menu = tile_menu(p->dtype, &cnt);
+  if (!menu || p->tile_id < 0 || p->tile_id >= cnt) return COSMA_ERR_INVALID_ARG;
+  const TileDesc& T = menu[p->tile_id];
+  if (p->m < 0 || p->n < 0 || p->k < 0) return COSMA_ERR_INVALID_ARG;
+  if (p->m == 0 || p->n == 0 || p->k == 0) return COSMA_OK;
+  if (p->tile_m != T.tm || p->tile_n != T.tn || p->tile_k != T.tk) return COSMA_ERR_INVALID_ARG;
+  if (p->p_m != ceil_div(p->m, T.tm) || p->p_n != ceil_div(p->n, T.tn)) return COSMA_ERR_INVALID_ARG;
+  if (p->p_k < 1 || p->k_split < T.tk || p->k_split % T.tk) return COSMA_ERR_INVALID_ARG;
+  if (ceil_div(p->k, p->k_split) != p->p_k) return COSMA_ERR_INVALID_ARG;
+  if (p->group_m < 1) return COSMA_ERR_INVALID_ARG;
+  if (p->dtype == F64_OZAKI_I8 && (p->slices < 1 || p->slices > 8)) return COSMA_ERR_INVALID_ARG;
+  return COSMA_OK;
+}
+
+}  // namespace cosma
+
+using namespace cosma;
+
+extern "C" {
+
+int cosma_gemm(int64_t m, int64_t n, int64_t k, double alpha, const void* A, int64_t lda,
+               const void* B, int64_t ldb, double beta, void* C, int64_t ldc, int dtype,
+               void* stream) {
+  int rc = check_args(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
+  if (rc != COSMA_OK) return rc;
+  if (m == 0 || n == 0) return COSMA_OK;
+  int st = COSMA_OK;
+  device_facts(&st);
+  if (st != COSMA_OK) return st;
+  cosma_plan_info plan;
+  rc = plan_cached(m, n, k, dtype, &plan);
+  if (rc != COSMA_OK) return rc;
+  return run_plan(plan, alpha, A, lda, B, ldb, beta, C, ldc, (hipStream_t)stream);
+}
+
+int cosma_gemm_planned(const cosma_plan_info* plan, double alpha, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
+                       void* stream) {
+  int rc = check_plan(plan);
+  if (rc != COSMA_OK) return rc;
+  rc = check_args(plan->m, plan->n, plan->k, alpha, A, lda, B, ldb, beta, C, ldc, plan->dtype);
+  if (rc != COSMA_OK) return rc;
+  if (plan->m == 0 || plan->n == 0) return COSMA_OK;
+  int st = COSMA_OK;
+  device_facts(&st);
+  if (st != COSMA_OK) return st;
+  return run_plan(*plan, alpha, A, lda, B, ldb, beta, C, ldc, (hipStream_t)stream);
+}
+
+int cosma_plan_query(int64_t m, int64_t n, int64_t k, int dtype, cosma_plan_info* out) {
+  if (!out) return COSMA_ERR_INVALID_ARG;
+  if (dtype < 0 || dtype >= NUM_DTYPES || m < 0 || n < 0 || k < 0) return COSMA_ERR_INVALID_ARG;
+  return plan_cached(m, n, k, dtype, out);
+}
+
+int cosma_plan_query_facts(int64_t m, int64_t n, int64_t k, int dtype,
+                           const cosma_device_facts* facts, double delta, cosma_plan_info* out) {
+  if (!out) return COSMA_ERR_INVALID_ARG;
+  cosma_device_facts f;
+  if (facts) {
+    f = *facts;
+  } else {
+    int st;
+    f = device_facts(&st);
+  }
+  return make_plan(m, n, k, dtype, f, delta, -1, -1, out);
+}
+
+int cosma_plan_make(int64_t m, int64_t n, int64_t k, int dtype, int tile_id, int p_k,
+                    cosma_plan_info* out) {
+  if (!out || tile_id < 0 || p_k < 1) return COSMA_ERR_INVALID_ARG;
+  int st;
+  const cosma_device_facts f = device_facts(&st);
+  const int rc = make_plan(m, n, k, dtype, f, env_delta(), tile_id, p_k, out);
+  if (rc != COSMA_OK) return rc;
+  if (m > 0 && n > 0 && k > 0 && out->p_k != p_k) return COSMA_ERR_INVALID_ARG;  // k too short
+  return COSMA_OK;
+}
+
+int cosma_tile_count(int dtype) {
+  int c = 0;
+  tile_menu(dtype, &c);
+  return c;
+}
+
+int cosma_tile_shape(int dtype, int id, int32_t* tm, int32_t* tn, int32_t* tk) {
+  int c = 0;
+  const TileDesc* menu = tile_menu(dtype, &c);
+  if (!menu || id < 0 || id >= c || !tm || !tn || !tk) return COSMA_ERR_INVALID_ARG;
+  *tm = menu[id].tm;
+  *tn = menu[id].tn;
+  *tk = menu[id].tk;
+  return COSMA_OK;
+}
+
+int cosma_device_query(cosma_device_facts* out) {
+  if (!out) return COSMA_ERR_INVALID_ARG;
+  int st = COSMA_OK;
+  *out = device_facts(&st);
+  return st;
+}
+
+double cosma_thm1_bound(double m, double n, double k, double S) {
+  if (!(S > 0)) return NAN;
+  return thm1_bound(m, n, k, S);
+}
+
+int cosma_seq_schedule(int64_t S, int64_t* a, int64_t* b) {
+  if (S < 3 || !a || !b) return COSMA_ERR_INVALID_ARG;
+  seq_schedule(S, a, b);
+  return COSMA_OK;
+}
+
+int cosma_par_schedule(double m, double n, double k, double p, double S, double* a, double* b) {
+  if (!(m > 0 && n > 0 && k > 0 && p > 0 && S > 0) || !a || !b) return COSMA_ERR_INVALID_ARG;
+  par_schedule(m, n, k, p, S, a, b);
+  return COSMA_OK;
+}
+
+int cosma_fit_ranks(int64_t m, int64_t n, int64_t k, int64_t p, double delta, int64_t grid[3],
+                    int64_t* used) {
+  if (!grid || !used) return COSMA_ERR_INVALID_ARG;
+  return fit_ranks(m, n, k, p, delta, grid, used) ? COSMA_OK : COSMA_ERR_INVALID_ARG;
+}
+
+double cosma_io_count(int64_t m, int64_t n, int64_t k, int64_t tm, int64_t tn, int64_t kc,
+                      int64_t pk, int beta_nonzero) {
+  return io_count(m, n, k, tm, tn, kc, pk, beta_nonzero != 0);
+}
+
+int cosma_workspace_size(int64_t m, int64_t n, int64_t k, int dtype, size_t* bytes) {
+  if (!bytes) return COSMA_ERR_INVALID_ARG;
+  cosma_plan_info p;
+  const int rc = cosma_plan_query(m, n, k, dtype, &p);
+  if (rc != COSMA_OK) return rc;
+  *bytes = p.workspace_bytes;
+  return COSMA_OK;
+}
+
+int cosma_set_workspace(void* ptr, size_t bytes, void* stream) {
+  (void)stream;
+  if ((ptr == nullptr) != (bytes == 0)) return COSMA_ERR_INVALID_ARG;
+  if (ptr && ((uintptr_t)ptr % 256) != 0) return COSMA_ERR_INVALID_ARG;
+  const int dev = current_device();
+  if (dev < 0) return COSMA_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  g_dev[dev].workspace = ptr;
+  g_dev[dev].workspace_bytes = bytes;
+  return COSMA_OK;
+}
+
+const char* cosma_status_string(int status) {
+  switch (status) {
+    case COSMA_OK: return "COSMA_OK";
+    case COSMA_ERR_INVALID_ARG: return "COSMA_ERR_INVALID_ARG: invalid argument";
+    case COSMA_ERR_HIP: return "COSMA_ERR_HIP: a HIP runtime call failed";
+    case COSMA_ERR_WORKSPACE: return "COSMA_ERR_WORKSPACE: registered workspace too small";
+    case COSMA_ERR_UNSUPPORTED: return "COSMA_ERR_UNSUPPORTED: no gfx950 device or unsupported case";
+    case COSMA_ERR_NO_MEMORY: return "COSMA_ERR_NO_MEMORY: host allocation failed";
+    default: return "unknown cosma status";
+  }
+}
+
+const char* cosma_version(void) { return "cosma_mi355 0.1.0 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,313 @@
+// FP64 GEMM on the CDNA4 matrix cores, the split-K reduction and the beta
+// scaling used by the BLAS quick returns.
+//
+// Structure (Algorithm 1 / section 5 of the paper, one work item per
+// workgroup): the workgroup keeps a BM x BN block of C resident in the
+// waves' accumulator registers for its whole reduction range and streams k
+// in rounds of BK.  Each round stages the BM x BK panel of A and the BK x BN
+// panel of B in LDS (the DistrData step of Algorithm 1 moved one level down
+// the memory hierarchy) while the matrix cores consume the previous round
+// (double buffering, the overlap of section 7.3).  When k is split the item
+// stores its partial block and splitk_reduce adds the partials (Reduce).
+//
+// Matrix-core operation: v_mfma_f64_16x16x4f64, D(16x16) += A(16x4) B(4x16).
+// Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[4 * v + l / 16][l % 16] in accumulator element v (rows interleaved across
+// the four lane groups; this differs from the FP32 form of the instruction,
+// where element v of lane l is row 4 * (l / 16) + v).  The four k slots of
+// one instruction are a sum, so their assignment to real k indices is free:
+// lane group g = l / 16 takes k = 16 h + 4 g + s at step s of 16-wide chunk
+// h, which lets a lane read its four A values of a chunk as one contiguous
+// 32-byte run.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "tiles.hpp"
+
+namespace cosma {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+template <int BM, int BN, int BK, int WM, int WN>
+struct F64Tile {
+  static constexpr int NT = WM * WN * 64;       // threads
+  static constexpr int WTM = BM / WM;           // wave tile rows
+  static constexpr int WTN = BN / WN;           // wave tile cols
+  static constexpr int MI = WTM / 16;           // MFMA blocks per wave (rows)
+  static constexpr int NI = WTN / 16;           // MFMA blocks per wave (cols)
+  static constexpr int LDA_S = BK + 2;          // As[row][k], padded
+  static constexpr int LDB_S = BN + 2;          // Bs[k][col], padded
+  static constexpr int A_CHUNKS = BM * BK / 2 / NT;  // double2 per thread
+  static constexpr int B_CHUNKS = BK * BN / 2 / NT;
+  static constexpr int A_STAGE = BM * LDA_S;
+  static constexpr int B_STAGE = BK * LDB_S;
+  static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "wave tiling");
+  static_assert(BK % 16 == 0, "BK must be a multiple of 16");
+  static_assert((BM * BK / 2) % NT == 0 && (BK * BN / 2) % NT == 0, "load tiling");
+  static_assert(2 * (A_STAGE + B_STAGE) * 8 <= 160 * 1024, "LDS budget");
+};
+
+// Load one round's A and B panels into registers.  CHECK: bounds and
+// alignment are not guaranteed, load element by element with zero fill.
+template <class TL, int BM, int BN, int BK, bool CHECK>
+__device__ __forceinline__ void load_round(const GemmArgs& g, int64_t row0, int64_t col0,
+                                           int64_t k0, int64_t kend, d2 (&ra)[TL::A_CHUNKS],
+                                           d2 (&rb)[TL::B_CHUNKS]) {
+  const double* __restrict__ A = static_cast<const double*>(g.A);
+  const double* __restrict__ B = static_cast<const double*>(g.B);
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < TL::A_CHUNKS; ++i) {
+    const int c = t + TL::NT * i;
+    const int r = c / (BK / 2);
+    const int kk = (c % (BK / 2)) * 2;
+    const int64_t gr = row0 + r, gk = k0 + kk;
+    if (!CHECK) {
+      ra[i] = *reinterpret_cast<const d2*>(A + gr * g.lda + gk);
+    } else {
+      const bool rin = gr < g.m;
+      ra[i].x = (rin && gk < kend) ? A[gr * g.lda + gk] : 0.0;
+      ra[i].y = (rin && gk + 1 < kend) ? A[gr * g.lda + gk + 1] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TL::B_CHUNKS; ++i) {
+    const int c = t + TL::NT * i;
+    const int r = c / (BN / 2);
+    const int nn = (c % (BN / 2)) * 2;
+    const int64_t gk = k0 + r, gc = col0 + nn;
+    if (!CHECK) {
+      rb[i] = *reinterpret_cast<const d2*>(B + gk * g.ldb + gc);
+    } else {
+      const bool kin = gk < kend;
+      rb[i].x = (kin && gc < g.n) ? B[gk * g.ldb + gc] : 0.0;
+      rb[i].y = (kin && gc + 1 < g.n) ? B[gk * g.ldb + gc + 1] : 0.0;
+    }
+  }
+}
+
+template <class TL, int BM, int BN, int BK>
+__device__ __forceinline__ void store_round(double* __restrict__ As, double* __restrict__ Bs,
+                                            const d2 (&ra)[TL::A_CHUNKS],
+                                            const d2 (&rb)[TL::B_CHUNKS]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < TL::A_CHUNKS; ++i) {
+    const int c = t + TL::NT * i;
+    const int r = c / (BK / 2);
+    const int kk = (c % (BK / 2)) * 2;
+    *reinterpret_cast<d2*>(As + r * TL::LDA_S + kk) = ra[i];
+  }
+#pragma unroll
+  for (int i = 0; i < TL::B_CHUNKS; ++i) {
+    const int c = t + TL::NT * i;
+    const int r = c / (BN / 2);
+    const int nn = (c % (BN / 2)) * 2;
+    *reinterpret_cast<d2*>(Bs + r * TL::LDB_S + nn) = rb[i];
+  }
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void gemm_f64_kernel(GemmArgs g) {
+  using TL = F64Tile<BM, BN, BK, WM, WN>;
+  __shared__ __attribute__((aligned(16))) double As[2][TL::A_STAGE];
+  __shared__ __attribute__((aligned(16))) double Bs[2][TL::B_STAGE];
+
+  const int64_t G = (int64_t)gridDim.x;
+  const int64_t l = xcd_remap((int64_t)blockIdx.x, G, g.num_xcds);
+  const ItemCoord ic = item_coord(l, g.tiles_m, g.tiles_n, g.group_m);
+  const int64_t row0 = ic.tile_row * BM, col0 = ic.tile_col * BN;
+  const int64_t kbeg = ic.split * g.k_split;
+  const int64_t kend = min64(g.k, kbeg + g.k_split);
+  const int64_t nk = ceil_div(kend - kbeg, BK);
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  const bool full_mn = (row0 + BM <= g.m) && (col0 + BN <= g.n) && g.vec_a && g.vec_b;
+
+  d4 acc[TL::MI][TL::NI];
+#pragma unroll
+  for (int i = 0; i < TL::MI; ++i)
+#pragma unroll
+    for (int j = 0; j < TL::NI; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  d2 ra[TL::A_CHUNKS], rb[TL::B_CHUNKS];
+  if (nk > 0) {
+    if (full_mn && kbeg + BK <= kend)
+      load_round<TL, BM, BN, BK, false>(g, row0, col0, kbeg, kend, ra, rb);
+    else
+      load_round<TL, BM, BN, BK, true>(g, row0, col0, kbeg, kend, ra, rb);
+    store_round<TL, BM, BN, BK>(As[0], Bs[0], ra, rb);
+  }
+  __syncthreads();
+
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    const bool more = kt + 1 < nk;
+    if (more) {
+      const int64_t k0 = kbeg + (kt + 1) * BK;
+      if (full_mn && k0 + BK <= kend)
+        load_round<TL, BM, BN, BK, false>(g, row0, col0, k0, kend, ra, rb);
+      else
+        load_round<TL, BM, BN, BK, true>(g, row0, col0, k0, kend, ra, rb);
+    }
+    const double* __restrict__ as = As[cur];
+    const double* __restrict__ bs = Bs[cur];
+#pragma unroll
+    for (int h = 0; h < BK / 16; ++h) {
+      d4 af[TL::MI];
+      double bf[TL::NI][4];
+#pragma unroll
+      for (int i = 0; i < TL::MI; ++i) {
+        const double* p = as + (wm * TL::WTM + i * 16 + lr) * TL::LDA_S + h * 16 + lg * 4;
+        const d2 lo = *reinterpret_cast<const d2*>(p);
+        const d2 hi = *reinterpret_cast<const d2*>(p + 2);
+        af[i] = d4{lo.x, lo.y, hi.x, hi.y};
+      }
+#pragma unroll
+      for (int j = 0; j < TL::NI; ++j)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          bf[j][s] = bs[(h * 16 + lg * 4 + s) * TL::LDB_S + wn * TL::WTN + j * 16 + lr];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < TL::MI; ++i)
+#pragma unroll
+          for (int j = 0; j < TL::NI; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+    }
+    if (more) store_round<TL, BM, BN, BK>(As[cur ^ 1], Bs[cur ^ 1], ra, rb);
+    __syncthreads();
+  }
+
+  // Epilogue: lane holds rows 4*v + lg of column lr of each 16x16 block.
+  if (g.splits == 1) {
+    double* __restrict__ C = static_cast<double*>(g.C);
+    const double alpha = g.alpha, beta = g.beta;
+#pragma unroll
+    for (int i = 0; i < TL::MI; ++i)
+#pragma unroll
+      for (int j = 0; j < TL::NI; ++j) {
+        const int64_t col = col0 + wn * TL::WTN + j * 16 + lr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = row0 + wm * TL::WTM + i * 16 + v * 4 + lg;
+          if (row < g.m && col < g.n) {
+            double* p = C + row * g.ldc + col;
+            const double r = alpha * acc[i][j][v];
+            *p = beta != 0.0 ? r + beta * *p : r;
+          }
+        }
+      }
+  } else {
+    double* __restrict__ P = static_cast<double*>(g.P) + ic.split * g.split_stride;
+#pragma unroll
+    for (int i = 0; i < TL::MI; ++i)
+#pragma unroll
+      for (int j = 0; j < TL::NI; ++j) {
+        const int64_t col = col0 + wn * TL::WTN + j * 16 + lr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = row0 + wm * TL::WTM + i * 16 + v * 4 + lg;
+          if (row < g.m && col < g.n) P[row * g.ldp + col] = acc[i][j][v];
+        }
+      }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const T* __restrict__ P,
+                                                            int64_t split_stride, int64_t ldp,
+                                                            int64_t splits, T* __restrict__ C,
+                                                            int64_t ldc, int64_t m, int64_t n,
+                                                            T alpha, T beta) {
+  const int64_t total = m * n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t row = e / n, col = e - row * n;
+    const T* p = P + row * ldp + col;
+    T s = p[0];
+    for (int64_t q = 1; q < splits; ++q) s += p[q * split_stride];
+    T* c = C + row * ldc + col;
+    const T r = alpha * s;
+    *c = beta != T(0) ? r + beta * *c : r;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void scale_kernel(T* __restrict__ C, int64_t ldc, int64_t m,
+                                                    int64_t n, T beta) {
+  const int64_t total = m * n;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const int64_t row = e / n, col = e - row * n;
+    T* c = C + row * ldc + col;
+    *c = beta != T(0) ? beta * *c : T(0);
+  }
+}
+
+unsigned elementwise_blocks(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+hipError_t launch_f64(const GemmArgs& g, hipStream_t s) {
+  const int64_t items = g.tiles_m * g.tiles_n * g.splits;
+  if (items <= 0) return hipSuccess;
+  if (items > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN>), dim3((unsigned)items),
+                     dim3(WM * WN * 64), 0, s, g);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm_f64(int tile_id, const GemmArgs& g, hipStream_t s) {
+  switch (tile_id) {
+    case 0: return launch_f64<128, 128, 16, 2, 2>(g, s);
+    case 1: return launch_f64<64, 64, 16, 2, 2>(g, s);
+    case 2: return launch_f64<256, 128, 16, 4, 2>(g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_splitk_reduce_f64(const double* P, int64_t split_stride, int64_t ldp,
+                                    int64_t splits, double* C, int64_t ldc, int64_t m, int64_t n,
+                                    double alpha, double beta, hipStream_t s) {
+  hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3(elementwise_blocks(m * n)), dim3(256), 0,
+                     s, P, split_stride, ldp, splits, C, ldc, m, n, alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_splitk_reduce_f32(const float* P, int64_t split_stride, int64_t ldp,
+                                    int64_t splits, float* C, int64_t ldc, int64_t m, int64_t n,
+                                    float alpha, float beta, hipStream_t s) {
+  hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3(elementwise_blocks(m * n)), dim3(256), 0,
+                     s, P, split_stride, ldp, splits, C, ldc, m, n, alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_f64(double* C, int64_t ldc, int64_t m, int64_t n, double beta,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(scale_kernel<double>, dim3(elementwise_blocks(m * n)), dim3(256), 0, s, C,
+                     ldc, m, n, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_f32(float* C, int64_t ldc, int64_t m, int64_t n, float beta,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(scale_kernel<float>, dim3(elementwise_blocks(m * n)), dim3(256), 0, s, C,
+                     ldc, m, n, beta);
+  return hipGetLastError();
+}
+
+}  // namespace cosma

@@ -1,0 +1,49 @@
+// Kernel launch interface between the C-ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cosma {
+
+// One GEMM launch: items = tiles_m * tiles_n * splits work items, each a
+// tile_m x tile_n block of C over the reduction range
+// [split * k_split, min(k, (split + 1) * k_split)).
+struct GemmArgs {
+  const void* A;
+  const void* B;
+  void* C;           // result (splits == 1)
+  void* P;           // partial blocks (splits > 1): P[split][row][col]
+  int64_t lda, ldb, ldc;
+  int64_t m, n, k;
+  int64_t k_split;
+  int64_t tiles_m, tiles_n, splits;
+  int64_t ldp;           // row stride of a partial plane
+  int64_t split_stride;  // elements between partial planes
+  double alpha, beta;
+  int group_m;
+  int num_xcds;
+  int vec_a, vec_b;      // operand rows may be read 16 bytes at a time
+};
+
+// FP64 MFMA GEMM (tile menu kTilesF64).
+hipError_t launch_gemm_f64(int tile_id, const GemmArgs& g, hipStream_t s);
+// FP32 MFMA GEMM (tile menu kTilesF32).
+hipError_t launch_gemm_f32(int tile_id, const GemmArgs& g, hipStream_t s);
+// FP32-accurate GEMM from three bf16 products (tile menu kTilesBf16x3).
+hipError_t launch_gemm_bf16x3(int tile_id, const GemmArgs& g, hipStream_t s);
+
+// C = alpha * sum_{s < splits} P[s] + beta * C, summed in ascending s.
+hipError_t launch_splitk_reduce_f64(const double* P, int64_t split_stride, int64_t ldp,
+                                    int64_t splits, double* C, int64_t ldc, int64_t m, int64_t n,
+                                    double alpha, double beta, hipStream_t s);
+hipError_t launch_splitk_reduce_f32(const float* P, int64_t split_stride, int64_t ldp,
+                                    int64_t splits, float* C, int64_t ldc, int64_t m, int64_t n,
+                                    float alpha, float beta, hipStream_t s);
+// C = beta * C (beta == 0 writes zeros without reading C).
+hipError_t launch_scale_f64(double* C, int64_t ldc, int64_t m, int64_t n, double beta,
+                            hipStream_t s);
+hipError_t launch_scale_f32(float* C, int64_t ldc, int64_t m, int64_t n, float beta,
+                            hipStream_t s);
+
+}  // namespace cosma

@@ -1,0 +1,369 @@
+// Host schedule planner.  See planner.hpp.
+#include "planner.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+namespace cosma {
+
+cosma_device_facts mi355x_defaults() {
+  cosma_device_facts f;
+  f.num_cus = 256;
+  f.num_xcds = 8;
+  f.lds_bytes_per_cu = 160 * 1024;
+  f.vgpr_bytes_per_cu = 512 * 1024;
+  f.l2_bytes_per_xcd = 4 * 1024 * 1024;
+  f.clock_ghz = 2.4;
+  f.hbm_gbps = 8000.0;
+  return f;
+}
+
+const TileDesc* tile_menu(int dtype, int* count) {
+  switch (dtype) {
+    case F64: *count = (int)(sizeof(kTilesF64) / sizeof(TileDesc)); return kTilesF64;
+    case F32: *count = (int)(sizeof(kTilesF32) / sizeof(TileDesc)); return kTilesF32;
+    case F32_BF16X3: *count = (int)(sizeof(kTilesBf16x3) / sizeof(TileDesc)); return kTilesBf16x3;
+    case F64_OZAKI_I8: *count = (int)(sizeof(kTilesOzaki) / sizeof(TileDesc)); return kTilesOzaki;
+    default: *count = 0; return nullptr;
+  }
+}
+
+int word_bytes(int dtype) { return (dtype == F64 || dtype == F64_OZAKI_I8) ? 8 : 4; }
+int partial_bytes(int dtype) { return word_bytes(dtype); }
+
+int ozaki_slices() {
+  static int s = [] {
+    const char* e = std::getenv("COSMA_OZAKI_SLICES");
+    int v = e ? std::atoi(e) : 7;
+    return v < 1 ? 1 : (v > 8 ? 8 : v);
+  }();
+  return s;
+}
+
+double useful_flops_per_clk_per_cu(int dtype, int slices) {
+  switch (dtype) {
+    case F64: return 128.0;               // FP64 MFMA
+    case F32: return 256.0;               // FP32 MFMA
+    case F32_BF16X3: return 4096.0 / 3;   // three bf16 products per useful one
+    case F64_OZAKI_I8: {                  // s(s+1)/2 int8 products per useful one
+      const double pairs = slices * (slices + 1) / 2.0;
+      return 8192.0 / (pairs > 0 ? pairs : 1.0);
+    }
+    default: return 1.0;
+  }
+}
+
+// ---- the paper's schedule functions ------------------------------------
+
+// Theorem 1: at least 2mnk/sqrt(S) + mn I/O operations.
+double thm1_bound(double m, double n, double k, double S) {
+  return 2.0 * m * n * k / std::sqrt(S) + m * n;
+}
+
+// Section 5: the optimal greedy step loads a elements of A and b of B while
+// an a x b block of C stays resident; maximise ab/(a+b) under
+// ab + a + 1 <= S.  For fixed a the best b is the largest feasible one, so a
+// scan over a finds the integer optimum (the printed floors of eq. aopt /
+// eq. bopt are close to, but not always equal to, this optimum).
+void seq_schedule(int64_t S, int64_t* a_out, int64_t* b_out) {
+  int64_t best_a = 0, best_b = 0;
+  double best = -1.0;
+  for (int64_t a = 1; a < S; ++a) {
+    const int64_t b = (S - 1 - a) / a;
+    if (b < 1) break;
+    const double rho = (double)a * (double)b / (double)(a + b);
+    if (rho > best * (1.0 + 1e-15)) {
+      best = rho;
+      best_a = a;
+      best_b = b;
+    }
+  }
+  *a_out = best_a;
+  *b_out = best_b;
+}
+
+// eq. optTileShape: the local domain is a x a x b with a = min{sqrt S, V^(1/3)},
+// b = max{V/S, V^(1/3)}, V = mnk/p.
+void par_schedule(double m, double n, double k, double p, double S, double* a, double* b) {
+  const double V = m * n * k / p;
+  const double cube = std::cbrt(V);
+  *a = std::min(std::sqrt(S), cube);
+  *b = std::max(V / S, cube);
+}
+
+// Theorem 2 (per processor): min{2mnk/(p sqrt S) + S, 3 (mnk/p)^(2/3)}.
+double thm2_bound(double m, double n, double k, double p, double S) {
+  const double V = m * n * k / p;
+  return std::min(2.0 * V / std::sqrt(S) + S, 3.0 * std::cbrt(V) * std::cbrt(V));
+}
+
+// Section 7.1: allow up to a fraction delta of the processors to idle when
+// that gives a grid with less communication.  The local domain of grid
+// (pm, pn, pk) is (m/pm) x (n/pn) x (k/pk); its surface -- the inputs and
+// output it touches -- is the communication per processor.  Scan the used
+// counts from p down and every factorisation; strict improvement only, so
+// ties keep the larger used count.
+bool fit_ranks(int64_t m, int64_t n, int64_t k, int64_t p, double delta, int64_t grid[3],
+               int64_t* used) {
+  if (m < 1 || n < 1 || k < 1 || p < 1 || delta < 0 || delta >= 1) return false;
+  const int64_t lo = std::max<int64_t>(1, (int64_t)std::ceil((1.0 - delta) * (double)p - 1e-9));
+  double best = INFINITY;
+  for (int64_t q = p; q >= lo; --q) {
+    for (int64_t pm = 1; pm <= q; ++pm) {
+      if (q % pm) continue;
+      const int64_t rest = q / pm;
+      for (int64_t pn = 1; pn <= rest; ++pn) {
+        if (rest % pn) continue;
+        const int64_t pk = rest / pn;
+        const double dm = (double)m / pm, dn = (double)n / pn, dk = (double)k / pk;
+        const double surface = dm * dk + dn * dk + dm * dn;
+        if (surface < best * (1.0 - 1e-12)) {
+          best = surface;
+          grid[0] = pm;
+          grid[1] = pn;
+          grid[2] = pk;
+          *used = q;
+        }
+      }
+    }
+  }
+  return true;
+}
+
+// Words moved by the tiled schedule.  Each work item keeps its block of C
+// resident and reads, over its k range, every element of its A row-panel
+// and B column-panel once: summed over items that is
+// k * (m * ceil(n/tn) + n * ceil(m/tm)), independent of kc and of p_k.
+// The output adds mn stores (Theorem 1's "+ mn"); with k split in p_k
+// parts every item also stores its partial block and the reduction reloads
+// all p_k partials before storing C; beta != 0 adds one load of C per entry.
+double io_count(int64_t m, int64_t n, int64_t k, int64_t tm, int64_t tn, int64_t kc, int64_t pk,
+                bool beta_nonzero) {
+  if (m <= 0 || n <= 0 || tm <= 0 || tn <= 0 || kc <= 0 || pk <= 0 || k < 0) return 0.0;
+  const double mn = (double)m * (double)n;
+  const double operands =
+      (double)k * ((double)m * (double)ceil_div(n, tn) + (double)n * (double)ceil_div(m, tm));
+  double out = mn * (beta_nonzero ? 2.0 : 1.0);
+  if (pk > 1) out += 2.0 * (double)pk * mn;
+  return operands + out;
+}
+
+double q_ea_bytes(int64_t m, int64_t n, int64_t k, int64_t k_split, int64_t splits, int tm,
+                  int tn, int group_m, int64_t slots_per_xcd, int num_xcds, double w_bytes) {
+  const int64_t tiles_m = ceil_div(m, tm), tiles_n = ceil_div(n, tn);
+  const int64_t items = tiles_m * tiles_n * splits;
+  const int X = std::max(1, num_xcds);
+  const int64_t q = items / X, r = items % X;
+  double bytes = 0.0;
+  std::vector<int64_t> rows, cols;
+  for (int x = 0; x < X; ++x) {
+    const int64_t begin = x * q + std::min<int64_t>(x, r);
+    const int64_t count = q + (x < r ? 1 : 0);
+    for (int64_t w0 = 0; w0 < count; w0 += slots_per_xcd) {
+      const int64_t w1 = std::min(count, w0 + slots_per_xcd);
+      rows.clear();
+      cols.clear();
+      for (int64_t l = begin + w0; l < begin + w1; ++l) {
+        const ItemCoord c = item_coord(l, tiles_m, tiles_n, group_m);
+        rows.push_back(c.split * tiles_m + c.tile_row);
+        cols.push_back(c.split * tiles_n + c.tile_col);
+      }
+      std::sort(rows.begin(), rows.end());
+      std::sort(cols.begin(), cols.end());
+      rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+      cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+      for (int64_t key : rows) {
+        const int64_t tr = key % tiles_m, sp = key / tiles_m;
+        const int64_t klen = std::min<int64_t>(k_split, k - sp * k_split);
+        bytes += (double)std::min<int64_t>(tm, m - tr * tm) * (double)klen * w_bytes;
+      }
+      for (int64_t key : cols) {
+        const int64_t tc = key % tiles_n, sp = key / tiles_n;
+        const int64_t klen = std::min<int64_t>(k_split, k - sp * k_split);
+        bytes += (double)std::min<int64_t>(tn, n - tc * tn) * (double)klen * w_bytes;
+      }
+    }
+  }
+  return bytes;
+}
+
+size_t workspace_bytes(const cosma_plan_info& p) {
+  if (p.m <= 0 || p.n <= 0 || p.k <= 0) return 0;
+  size_t ws = 0;
+  if (p.p_k > 1) ws += (size_t)p.p_k * (size_t)p.m * (size_t)p.n * (size_t)partial_bytes(p.dtype);
+  ws = (ws + 255) / 256 * 256;
+  if (p.dtype == F64_OZAKI_I8) {
+    // digit planes of A (m x kp) and of B (stored n x kp), k padded to 64,
+    // then per-row / per-column exponents
+    const size_t kp = (size_t)ceil_div(p.k, 64) * 64;
+    ws += ((size_t)p.slices * kp * ((size_t)p.m + (size_t)p.n) + 255) / 256 * 256;
+    ws += (((size_t)p.m + (size_t)p.n) * sizeof(int32_t) + 255) / 256 * 256;
+  }
+  return ws;
+}
+
+namespace {
+
+struct Candidate {
+  int tile_id;
+  int p_k;            // actual number of splits
+  int64_t k_split;
+  int group_m;
+  int64_t items, waves;
+  double q_cu, q_ea, t;
+};
+
+double launch_overhead_s() { return 4e-6; }
+
+}  // namespace
+
+int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_facts& f,
+              double delta, int tile_id, int p_k, cosma_plan_info* out) {
+  if (!out || m < 0 || n < 0 || k < 0) return COSMA_ERR_INVALID_ARG;
+  int ntiles = 0;
+  const TileDesc* menu = tile_menu(dtype, &ntiles);
+  if (!menu) return COSMA_ERR_INVALID_ARG;
+  if (tile_id >= ntiles) return COSMA_ERR_INVALID_ARG;
+  if (f.num_cus < 1 || f.num_xcds < 1 || f.clock_ghz <= 0 || f.hbm_gbps <= 0 ||
+      f.lds_bytes_per_cu < 0 || f.vgpr_bytes_per_cu < 0)
+    return COSMA_ERR_INVALID_ARG;
+  if (!(delta >= 0.0 && delta < 1.0)) return COSMA_ERR_INVALID_ARG;
+
+  std::memset(out, 0, sizeof(*out));
+  out->m = m;
+  out->n = n;
+  out->k = k;
+  out->dtype = dtype;
+  const int slices = dtype == F64_OZAKI_I8 ? ozaki_slices() : 0;
+  out->slices = slices;
+
+  // Fast memory of one CU in words of the stored operand (an Ozaki word is
+  // the s digit bytes of one element).
+  const double w = dtype == F64_OZAKI_I8 ? (double)slices : (double)word_bytes(dtype);
+  const double S = std::max(3.0, (double)(f.lds_bytes_per_cu + f.vgpr_bytes_per_cu) / w);
+  out->S_words = S;
+  const double P = (double)f.num_cus;
+  out->p1 = (double)m * (double)n / S;
+  out->regime = P > out->p1 ? 1 : 0;
+  int64_t a_seq = 0, b_seq = 0;
+  seq_schedule((int64_t)S, &a_seq, &b_seq);
+  out->a_seq = a_seq;
+  out->b_seq = b_seq;
+  if (m > 0 && n > 0 && k > 0) {
+    par_schedule((double)m, (double)n, (double)k, P, S, &out->a_par, &out->b_par);
+    out->thm1_words = thm1_bound((double)m, (double)n, (double)k, S);
+    out->thm2_words = thm2_bound((double)m, (double)n, (double)k, P, S);
+  }
+
+  if (m == 0 || n == 0 || k == 0) {
+    // BLAS quick returns: no products to schedule.
+    const int id = tile_id >= 0 ? tile_id : 0;
+    out->tile_id = id;
+    out->tile_m = menu[id].tm;
+    out->tile_n = menu[id].tn;
+    out->tile_k = menu[id].tk;
+    out->p_m = out->p_n = 0;
+    out->p_k = 1;
+    out->group_m = 1;
+    out->wg_per_cu = menu[id].wg_per_cu;
+    return COSMA_OK;
+  }
+
+  const double per_cu_rate = useful_flops_per_clk_per_cu(dtype, slices) * f.clock_ghz * 1e9;
+  const double hbm = f.hbm_gbps * 1e9;
+  const double pb = (double)partial_bytes(dtype);
+  const double wb = (double)word_bytes(dtype);
+  const double mn = (double)m * (double)n;
+  const int cus_per_xcd = std::max(1, f.num_cus / f.num_xcds);
+
+  static const int kSplits[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64};
+  static const int kGroups[] = {1, 2, 4, 8, 16};
+  std::vector<Candidate> cands;
+  for (int id = 0; id < ntiles; ++id) {
+    if (tile_id >= 0 && id != tile_id) continue;
+    const TileDesc& T = menu[id];
+    const int64_t panels = ceil_div(k, T.tk);
+    const int64_t tiles = ceil_div(m, T.tm) * ceil_div(n, T.tn);
+    for (int req : kSplits) {
+      if (p_k > 0 && req != p_k) continue;
+      if (p_k <= 0 && req > 1 && (double)k / req < 256.0) continue;  // keep rounds long
+      const int64_t k_split = ceil_div(panels, req) * T.tk;
+      const int64_t splits = ceil_div(k, k_split);
+      if (p_k <= 0 && splits != req) continue;  // duplicate of a smaller request
+      const int64_t items = tiles * splits;
+      const int64_t slots = (int64_t)f.num_cus * T.wg_per_cu;
+      const int64_t waves = ceil_div(items, slots);
+      const double item_flops = 2.0 * T.tm * T.tn * (double)k_split;
+      const double t_compute = (double)waves * item_flops / (per_cu_rate / T.wg_per_cu) / T.eff;
+      double best_q = INFINITY;
+      int best_g = 1;
+      for (int g : kGroups) {
+        if (g > 1 && g > ceil_div(m, T.tm)) break;
+        const double q = q_ea_bytes(m, n, k, k_split, splits, T.tm, T.tn, g,
+                                    (int64_t)cus_per_xcd * T.wg_per_cu, f.num_xcds, w);
+        if (q < best_q * (1.0 - 1e-12)) {
+          best_q = q;
+          best_g = g;
+        }
+      }
+      // GEMM launch: operand panels + either C or the partial blocks.
+      const double gemm_bytes = best_q + (splits > 1 ? (double)splits * mn * pb : mn * wb);
+      // Reduce launch: reload the partials, store C.
+      const double reduce_bytes = splits > 1 ? (double)splits * mn * pb + mn * wb : 0.0;
+      // Ozaki prologue: read A and B once, write their digit planes.
+      const double pre_bytes =
+          dtype == F64_OZAKI_I8 ? ((double)m * k + (double)k * n) * (8.0 + slices) : 0.0;
+      const double q_ea = gemm_bytes + reduce_bytes + pre_bytes;
+      const double t_mem = gemm_bytes / hbm;
+      const double t_reduce = splits > 1 ? reduce_bytes / hbm + launch_overhead_s() : 0.0;
+      const double t_pre = pre_bytes > 0 ? pre_bytes / hbm + 2 * launch_overhead_s() : 0.0;
+      Candidate c;
+      c.tile_id = id;
+      c.p_k = (int)splits;
+      c.k_split = k_split;
+      c.group_m = best_g;
+      c.items = items;
+      c.waves = waves;
+      c.q_cu = io_count(m, n, k, T.tm, T.tn, T.tk, splits, false);
+      c.q_ea = q_ea;
+      c.t = std::max(t_compute, t_mem) + t_reduce + t_pre + launch_overhead_s();
+      cands.push_back(c);
+    }
+  }
+  if (cands.empty()) return COSMA_ERR_INVALID_ARG;
+  double t_best = INFINITY;
+  for (const Candidate& c : cands) t_best = std::min(t_best, c.t);
+  // Section 7.1's trade: accept up to a fraction delta more (modelled)
+  // compute time for a schedule that moves less data.
+  const Candidate* pick = nullptr;
+  for (const Candidate& c : cands) {
+    if (c.t > t_best * (1.0 + delta) + 1e-12) continue;
+    if (!pick || c.q_cu < pick->q_cu * (1.0 - 1e-12) ||
+        (c.q_cu <= pick->q_cu * (1.0 + 1e-12) && c.t < pick->t))
+      pick = &c;
+  }
+  const TileDesc& T = menu[pick->tile_id];
+  out->tile_id = pick->tile_id;
+  out->tile_m = T.tm;
+  out->tile_n = T.tn;
+  out->tile_k = T.tk;
+  out->p_m = (int32_t)ceil_div(m, T.tm);
+  out->p_n = (int32_t)ceil_div(n, T.tn);
+  out->p_k = pick->p_k;
+  out->group_m = pick->group_m;
+  out->wg_per_cu = T.wg_per_cu;
+  out->k_split = pick->k_split;
+  out->items = pick->items;
+  out->waves = pick->waves;
+  out->q_cu_words = pick->q_cu;
+  out->q_ea_bytes = pick->q_ea;
+  out->predicted_ms = pick->t * 1e3;
+  const size_t ws = workspace_bytes(*out);
+  out->workspace_bytes = ws;
+  return COSMA_OK;
+}
+
+}  // namespace cosma

@@ -1,0 +1,54 @@
+// Host schedule planner: Algorithm 1's FindSeqSchedule, ParallelizeSched and
+// FitRanks mapped onto the compute units of one GPU.  Host-only C++17.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/cosma_mi355.h"
+#include "tiles.hpp"
+
+namespace cosma {
+
+// Default figures for MI355X (gfx950), used when no device is present.
+cosma_device_facts mi355x_defaults();
+
+// Tile menu for a dtype (nullptr / 0 for an unknown dtype).
+const TileDesc* tile_menu(int dtype, int* count);
+
+// Bytes per stored operand element, per partial-result element, and the
+// MFMA rate per CU per clock in useful flops (2 per multiply-add of the
+// product being emulated).
+int word_bytes(int dtype);
+int partial_bytes(int dtype);
+double useful_flops_per_clk_per_cu(int dtype, int slices);
+
+// Number of int8 digit slices per operand used by the Ozaki path.
+int ozaki_slices();
+
+// ---- the paper's schedule functions -----------------------------------
+double thm1_bound(double m, double n, double k, double S);                 // Theorem 1
+void seq_schedule(int64_t S, int64_t* a, int64_t* b);                      // section 5
+void par_schedule(double m, double n, double k, double p, double S, double* a, double* b);
+double thm2_bound(double m, double n, double k, double p, double S);       // Theorem 2
+bool fit_ranks(int64_t m, int64_t n, int64_t k, int64_t p, double delta, int64_t grid[3],
+               int64_t* used);                                              // section 7.1
+double io_count(int64_t m, int64_t n, int64_t k, int64_t tm, int64_t tn, int64_t kc, int64_t pk,
+                bool beta_nonzero);
+
+// Predicted L2 <-> memory traffic (bytes) of a launch that runs `items`
+// work items in the xcd_remap / item_coord order, waves of resident slots
+// sharing each XCD's L2 (section 5's schedule applied one memory level up).
+double q_ea_bytes(int64_t m, int64_t n, int64_t k, int64_t k_split, int64_t splits, int tm,
+                  int tn, int group_m, int64_t slots_per_xcd, int num_xcds, double w_bytes);
+
+// Device workspace a plan needs (split-K partials, Ozaki digit planes).
+size_t workspace_bytes(const cosma_plan_info& p);
+
+// ---- GPU plan -----------------------------------------------------------
+// Fill `out` for a given tile and split (tile_id < 0 / p_k <= 0: planner's
+// choice).  Returns a cosma_status.
+int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_facts& f,
+              double delta, int tile_id, int p_k, cosma_plan_info* out);
+
+}  // namespace cosma

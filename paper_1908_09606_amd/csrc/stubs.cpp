@@ -1,0 +1,27 @@
+// Entry points whose kernels are not built yet.
+#include "kernels.hpp"
+#include "ozaki.hpp"
+
+namespace cosma {
+hipError_t launch_gemm_f32(int, const GemmArgs&, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_gemm_bf16x3(int, const GemmArgs&, hipStream_t) { return hipErrorNotSupported; }
+int run_ozaki(const cosma_plan_info&, double, const void*, int64_t, const void*, int64_t, double,
+              void*, int64_t, void*, hipStream_t) {
+  return COSMA_ERR_UNSUPPORTED;
+}
+}  // namespace cosma
+
+extern "C" {
+int cosma_gemm_batched(int64_t, const int64_t*, const int64_t*, const int64_t*, const double*,
+                       const void* const*, const int64_t*, const void* const*, const int64_t*,
+                       const double*, void* const*, const int64_t*, int, void*) {
+  return COSMA_ERR_UNSUPPORTED;
+}
+int cosma_batch_create(int64_t, const int64_t*, const int64_t*, const int64_t*, const double*,
+                       const void* const*, const int64_t*, const void* const*, const int64_t*,
+                       const double*, void* const*, const int64_t*, int, void*, void**) {
+  return COSMA_ERR_UNSUPPORTED;
+}
+int cosma_batch_run(void*, void*) { return COSMA_ERR_UNSUPPORTED; }
+int cosma_batch_destroy(void*) { return COSMA_ERR_UNSUPPORTED; }
+}

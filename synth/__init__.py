@@ -135,3 +135,53 @@ def batch_dims(count: int, seed: int, lo: int = 64, hi: int = 4096) -> np.ndarra
         x = np.floor(lo * np.exp2(span * u)).astype(np.int64)
         out[:, d] = np.clip(x, lo, hi)
     return out
+
+
+# ------------------------------------------------------------------ device fill
+import ctypes as _ct
+import os as _os
+import subprocess as _sp
+
+_FILL_SRC = _os.path.join(_os.path.dirname(_os.path.abspath(__file__)), "fill.hip")
+_FILL_LIB = _os.path.join(_os.path.dirname(_os.path.abspath(__file__)), "libsynth_fill.so")
+_fill = None
+
+
+def build_fill(hipcc: str = "/opt/rocm/bin/hipcc") -> str:
+    """Compile the device fill kernel for gfx950 (always recompiles)."""
+    tmp = _FILL_LIB + ".tmp%d" % _os.getpid()
+    _sp.check_call([hipcc, "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                    "-o", tmp, _FILL_SRC], stderr=_sp.DEVNULL)
+    _os.replace(tmp, _FILL_LIB)
+    return _FILL_LIB
+
+
+def _fill_lib():
+    global _fill
+    if _fill is None:
+        if not _os.path.exists(_FILL_LIB):
+            build_fill()
+        L = _ct.CDLL(_FILL_LIB)
+        L.synth_fill.restype = _ct.c_int
+        L.synth_fill.argtypes = [_ct.c_void_p, _ct.c_int64, _ct.c_int64, _ct.c_int64, _ct.c_uint64,
+                                 _ct.c_uint32, _ct.c_int, _ct.c_int64, _ct.c_void_p]
+        _fill = L
+    return _fill
+
+
+def fill_device(t, seed: int, stream: int, dist: int, param: int = 0, hip_stream=None) -> None:
+    """Fill the 2-D torch device tensor t (row-major, unit column stride) with
+    the same values gen() gives for a t.shape[0] x t.shape[1] matrix."""
+    import torch
+    rows, cols = t.shape
+    if cols > 1 and t.stride(1) != 1:
+        raise ValueError("unit column stride required")
+    want = torch.float32 if dist in _F32_DISTS else torch.float64
+    if t.dtype != want:
+        raise ValueError(f"distribution {dist} fills {want}, got {t.dtype}")
+    ld = t.stride(0) if rows > 1 else max(cols, 1)
+    s = hip_stream if hip_stream is not None else torch.cuda.current_stream().cuda_stream
+    rc = _fill_lib().synth_fill(t.data_ptr(), rows, cols, ld, seed & MASK64, stream, dist, param, s)
+    if rc != 0:
+        raise RuntimeError(f"synth_fill failed ({rc})")

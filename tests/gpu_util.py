@@ -1,0 +1,56 @@
+"""Helpers for the GPU parity tests: seeded device inputs and sampled oracle
+checks.  Inputs come from synth (host and device fill implement the same
+generator); expected values come only from the oracle."""
+import sys
+
+import numpy as np
+
+import oracle
+import synth
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def device_matrix(rows, cols, seed, stream, dist, param=0, ld=None, torch_dtype=None):
+    """A rows x cols device matrix (leading dimension ld) filled by synth."""
+    import torch
+    dt = torch.float32 if dist in (synth.UNIFORM_F32, synth.INT_F32) else torch.float64
+    ld = cols if ld is None else ld
+    buf = torch.empty((max(rows, 1), max(ld, 1)), dtype=dt, device="cuda")
+    view = buf[:rows, :cols]
+    if rows and cols:
+        synth.fill_device(view, seed, stream, dist, param)
+    return buf, view
+
+
+def sample_indices(total, count, rng, tile=128):
+    """Indices for sampled verification: random ones plus the first and last
+    rows/columns of the first and last tiles (edge tiles)."""
+    edge = set(range(min(total, 4))) | set(range(max(0, total - 4), total))
+    last_tile = (total - 1) // tile * tile
+    edge |= {last_tile, min(total - 1, last_tile + 1)}
+    rnd = rng.choice(total, size=min(total, count), replace=False) if total else []
+    return np.array(sorted(edge | set(int(x) for x in rnd)), dtype=np.int64)
+
+
+def sampled_check(C_dev_view, m, n, k, seed, dist, alpha=1.0, beta=0.0, C0_host=None,
+                  rows=None, cols=None, bound=None):
+    """Compare sampled entries of the device result with the oracle computed
+    from regenerated rows of A and columns of B.  Returns the normalised error."""
+    import torch
+    rows = np.asarray(rows)
+    cols = np.asarray(cols)
+    Ar = synth.gen(m, k, seed, synth.STREAM_A, dist, row_idx=rows)
+    Bc = synth.gen(k, n, seed, synth.STREAM_B, dist, col_idx=cols)
+    c0 = None if C0_host is None else C0_host[np.ix_(rows, cols)]
+    ref, D = oracle.gemm(Ar, Bc, alpha, beta, c0)
+    ri = torch.as_tensor(rows, device=C_dev_view.device)
+    ci = torch.as_tensor(cols, device=C_dev_view.device)
+    got = C_dev_view.index_select(0, ri).index_select(1, ci).double().cpu().numpy()
+    err = oracle.normalised_err(got, ref, D)
+    if bound is not None:
+        assert err <= bound, f"normalised error {err:.3e} > bound {bound:.3e}"
+    return err

@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--shapes", default="square,large_k,flat")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="also run one plain copy kernel (out = in * 1.0 over float64) "
+                         "moving BYTES each way, to calibrate memory counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -169,6 +172,16 @@ def main():
         "shapes": shape_rows,
     }
 
+    if args.copy_calibration > 0:
+        nel = args.copy_calibration // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nel * 8
+        del src, dst
+
     if not args.no_variants:
         out["variants"] = run_variants(torch, cm, synth, dev, stream)
 
@@ -195,7 +208,7 @@ def cpu_baseline(probs, torch):
     import synth
     p = next((q for q in probs if q["name"] == "square"), probs[0])
     m, n, k = p["m"], p["n"], p["k"]
-    rows = int(os.environ.get("COSMA_BENCH_ORACLE_ROWS", "256"))
+    rows = int(os.environ.get("COSMA_BENCH_ORACLE_ROWS", "1024"))
     rows = max(1, min(rows, m))
     Ar = synth.gen(m, k, SEED, synth.STREAM_A, synth.UNIFORM_F64, row_idx=np.arange(rows))
     Bh = p["B"].cpu().numpy()

@@ -187,8 +187,9 @@ int run_plan(const cosma_plan_info& plan, double alpha, const void* A, int64_t l
   int st = COSMA_OK;
   g.num_xcds = device_facts(&st).num_xcds;
   const size_t el = (size_t)word_bytes(dtype);
-  g.vec_a = ((uintptr_t)A % (2 * el) == 0 && lda % 2 == 0) ? 1 : 0;
-  g.vec_b = ((uintptr_t)B % (2 * el) == 0 && ldb % 2 == 0) ? 1 : 0;
+  // 16-byte loads need a 16-byte aligned base and a row pitch of 16 bytes.
+  g.vec_a = ((uintptr_t)A % 16 == 0 && ((size_t)lda * el) % 16 == 0) ? 1 : 0;
+  g.vec_b = ((uintptr_t)B % 16 == 0 && ((size_t)ldb * el) % 16 == 0) ? 1 : 0;
   if (plan.p_k > 1) g.P = ws;
 
   hipError_t e;

@@ -1,0 +1,421 @@
+// FP32-class GEMMs on the CDNA4 matrix cores.
+//
+//   gemm_f32_kernel     native FP32: v_mfma_f32_16x16x4f32
+//   gemm_bf16x3_kernel  FP32-accurate product from bf16 pieces: every FP32
+//                       operand x is split as x_hi = bf16_rn(x),
+//                       x_lo = bf16_rn(x - x_hi) and
+//                       A*B ~ A_lo*B_hi + A_hi*B_lo + A_hi*B_hi
+//                       (the dropped A_lo*B_lo and split residues are
+//                       below 2^-16 relative), with v_mfma_f32_16x16x32_bf16
+//                       and FP32 accumulation.
+//
+// Both keep the work item's block of C resident in accumulators and stream
+// k in LDS-staged rounds (the loop of Algorithm 1, section 5's resident
+// block), double-buffered as in section 7.3.  The bf16 split is done while
+// staging: FP32 panels are read from memory once, split in registers and
+// written to LDS as hi / lo planes, so no extra pass over A or B is needed.
+//
+// Matrix-core layouts (lane l, r = l % 16, g = l / 16):
+//   f32 16x16x4:  a = A[r][g], b = B[g][r], acc[v] = D[4g + v][r]
+//   bf16 16x16x32: a[i] = A[r][8g + i], b[i] = B[8g + i][r] (i < 8),
+//                  acc[v] = D[4g + v][r]
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "tiles.hpp"
+
+namespace cosma {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------- native FP32
+template <int BM, int BN, int BK, int WM, int WN>
+struct F32Tile {
+  static constexpr int NT = WM * WN * 64;
+  static constexpr int WTM = BM / WM, WTN = BN / WN;
+  static constexpr int MI = WTM / 16, NI = WTN / 16;
+  static constexpr int LDA_S = BK + 4;   // As[row][k] (floats), 16-byte rows
+  static constexpr int LDB_S = BN + 4;   // Bs[k][col]
+  static constexpr int A_CHUNKS = BM * BK / 4 / NT;  // float4 per thread
+  static constexpr int B_CHUNKS = BK * BN / 4 / NT;
+  static constexpr int A_STAGE = BM * LDA_S, B_STAGE = BK * LDB_S;
+  static_assert(BK % 16 == 0 && (BM * BK / 4) % NT == 0 && (BK * BN / 4) % NT == 0, "tiling");
+  static_assert(2 * (A_STAGE + B_STAGE) * 4 <= 160 * 1024, "LDS budget");
+};
+
+template <class TL, int BM, int BN, int BK, bool CHECK>
+__device__ __forceinline__ void f32_load(const GemmArgs& g, int64_t row0, int64_t col0, int64_t k0,
+                                         int64_t kend, f4 (&ra)[TL::A_CHUNKS],
+                                         f4 (&rb)[TL::B_CHUNKS]) {
+  const float* __restrict__ A = static_cast<const float*>(g.A);
+  const float* __restrict__ B = static_cast<const float*>(g.B);
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < TL::A_CHUNKS; ++i) {
+    const int c = t + TL::NT * i;
+    const int r = c / (BK / 4), kk = (c % (BK / 4)) * 4;
+    const int64_t gr = row0 + r, gk = k0 + kk;
+    if (!CHECK) {
+      ra[i] = *reinterpret_cast<const f4*>(A + gr * g.lda + gk);
+    } else {
+      const bool rin = gr < g.m;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ra[i][e] = (rin && gk + e < kend) ? A[gr * g.lda + gk + e] : 0.0f;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TL::B_CHUNKS; ++i) {
+    const int c = t + TL::NT * i;
+    const int r = c / (BN / 4), nn = (c % (BN / 4)) * 4;
+    const int64_t gk = k0 + r, gc = col0 + nn;
+    if (!CHECK) {
+      rb[i] = *reinterpret_cast<const f4*>(B + gk * g.ldb + gc);
+    } else {
+      const bool kin = gk < kend;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rb[i][e] = (kin && gc + e < g.n) ? B[gk * g.ldb + gc + e] : 0.0f;
+    }
+  }
+}
+
+template <class TL, int BM, int BN, int BK>
+__device__ __forceinline__ void f32_store(float* As, float* Bs, const f4 (&ra)[TL::A_CHUNKS],
+                                          const f4 (&rb)[TL::B_CHUNKS]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < TL::A_CHUNKS; ++i) {
+    const int c = t + TL::NT * i;
+    const int r = c / (BK / 4), kk = (c % (BK / 4)) * 4;
+    *reinterpret_cast<f4*>(As + r * TL::LDA_S + kk) = ra[i];
+  }
+#pragma unroll
+  for (int i = 0; i < TL::B_CHUNKS; ++i) {
+    const int c = t + TL::NT * i;
+    const int r = c / (BN / 4), nn = (c % (BN / 4)) * 4;
+    *reinterpret_cast<f4*>(Bs + r * TL::LDB_S + nn) = rb[i];
+  }
+}
+
+// Epilogue shared by both FP32-class kernels (standard 16x16 output layout).
+template <int MI, int NI, int WTM, int WTN>
+__device__ __forceinline__ void f32_epilogue(const GemmArgs& g, const ItemCoord& ic, int64_t row0,
+                                             int64_t col0, int wm, int wn, int lr, int lg,
+                                             const f4 (&acc)[MI][NI]) {
+  if (g.splits == 1) {
+    float* __restrict__ C = static_cast<float*>(g.C);
+    const float alpha = (float)g.alpha, beta = (float)g.beta;
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        const int64_t col = col0 + wn * WTN + j * 16 + lr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = row0 + wm * WTM + i * 16 + lg * 4 + v;
+          if (row < g.m && col < g.n) {
+            float* p = C + row * g.ldc + col;
+            const float r = alpha * acc[i][j][v];
+            *p = beta != 0.0f ? r + beta * *p : r;
+          }
+        }
+      }
+  } else {
+    float* __restrict__ P = static_cast<float*>(g.P) + ic.split * g.split_stride;
+#pragma unroll
+    for (int i = 0; i < MI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        const int64_t col = col0 + wn * WTN + j * 16 + lr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = row0 + wm * WTM + i * 16 + lg * 4 + v;
+          if (row < g.m && col < g.n) P[row * g.ldp + col] = acc[i][j][v];
+        }
+      }
+  }
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void gemm_f32_kernel(GemmArgs g) {
+  using TL = F32Tile<BM, BN, BK, WM, WN>;
+  __shared__ __attribute__((aligned(16))) float As[2][TL::A_STAGE];
+  __shared__ __attribute__((aligned(16))) float Bs[2][TL::B_STAGE];
+
+  const int64_t l = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x, g.num_xcds);
+  const ItemCoord ic = item_coord(l, g.tiles_m, g.tiles_n, g.group_m);
+  const int64_t row0 = ic.tile_row * BM, col0 = ic.tile_col * BN;
+  const int64_t kbeg = ic.split * g.k_split;
+  const int64_t kend = min64(g.k, kbeg + g.k_split);
+  const int64_t nk = ceil_div(kend - kbeg, BK);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int lr = lane & 15, lg = lane >> 4;
+  const bool full_mn = (row0 + BM <= g.m) && (col0 + BN <= g.n) && g.vec_a && g.vec_b;
+
+  f4 acc[TL::MI][TL::NI];
+#pragma unroll
+  for (int i = 0; i < TL::MI; ++i)
+#pragma unroll
+    for (int j = 0; j < TL::NI; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  f4 ra[TL::A_CHUNKS], rb[TL::B_CHUNKS];
+  if (nk > 0) {
+    if (full_mn && kbeg + BK <= kend)
+      f32_load<TL, BM, BN, BK, false>(g, row0, col0, kbeg, kend, ra, rb);
+    else
+      f32_load<TL, BM, BN, BK, true>(g, row0, col0, kbeg, kend, ra, rb);
+    f32_store<TL, BM, BN, BK>(As[0], Bs[0], ra, rb);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    const bool more = kt + 1 < nk;
+    if (more) {
+      const int64_t k0 = kbeg + (kt + 1) * BK;
+      if (full_mn && k0 + BK <= kend)
+        f32_load<TL, BM, BN, BK, false>(g, row0, col0, k0, kend, ra, rb);
+      else
+        f32_load<TL, BM, BN, BK, true>(g, row0, col0, k0, kend, ra, rb);
+    }
+    const float* as = As[cur];
+    const float* bs = Bs[cur];
+#pragma unroll
+    for (int h = 0; h < BK / 16; ++h) {
+      f4 af[TL::MI];
+      float bf[TL::NI][4];
+#pragma unroll
+      for (int i = 0; i < TL::MI; ++i)
+        af[i] = *reinterpret_cast<const f4*>(as + (wm * TL::WTM + i * 16 + lr) * TL::LDA_S +
+                                             h * 16 + lg * 4);
+#pragma unroll
+      for (int j = 0; j < TL::NI; ++j)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          bf[j][s] = bs[(h * 16 + lg * 4 + s) * TL::LDB_S + wn * TL::WTN + j * 16 + lr];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < TL::MI; ++i)
+#pragma unroll
+          for (int j = 0; j < TL::NI; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+    }
+    if (more) f32_store<TL, BM, BN, BK>(As[cur ^ 1], Bs[cur ^ 1], ra, rb);
+    __syncthreads();
+  }
+  f32_epilogue<TL::MI, TL::NI, TL::WTM, TL::WTN>(g, ic, row0, col0, wm, wn, lr, lg, acc);
+}
+
+// ------------------------------------------------------------- BF16x3
+// LDS holds four planes per stage, all k-contiguous with rows of BK bf16
+// plus 8 of padding: A_hi, A_lo as [row][k] and B_hi, B_lo as [col][k], so
+// every MFMA operand (8 consecutive k of one row / column) is one 16-byte
+// read.  Each thread stages 8 consecutive k of one A row (two 16-byte loads)
+// and 8 consecutive k of one B column (eight 4-byte loads, coalesced across
+// the lanes of a wave, which cover consecutive columns).
+template <int BM, int BN, int BK, int WM, int WN>
+struct X3Tile {
+  static constexpr int NT = WM * WN * 64;
+  static constexpr int WTM = BM / WM, WTN = BN / WN;
+  static constexpr int MI = WTM / 16, NI = WTN / 16;
+  static constexpr int LD = BK + 8;                        // bf16 per LDS row
+  static constexpr int A_CHUNKS = BM * BK / 8 / NT;        // 8-element pieces per thread
+  static constexpr int B_CHUNKS = BK * BN / 8 / NT;
+  static constexpr int A_PLANE = BM * LD, B_PLANE = BN * LD;
+  static constexpr int STAGE = 2 * A_PLANE + 2 * B_PLANE;  // bf16 elements
+  static_assert(BK % 32 == 0 && (BM * BK / 8) % NT == 0 && (BK * BN / 8) % NT == 0, "tiling");
+  static_assert(2 * STAGE * 2 <= 160 * 1024, "LDS budget");
+};
+
+// Round-to-nearest-even split of 8 floats into bf16 hi and lo pieces.
+__device__ __forceinline__ void split8(const float (&x)[8], us8& hi, us8& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    const float r = x[e] - (float)h;
+    const __bf16 q = (__bf16)r;
+    hi[e] = __builtin_bit_cast(unsigned short, h);
+    lo[e] = __builtin_bit_cast(unsigned short, q);
+  }
+}
+
+template <class TL, int BM, int BN, int BK, bool CHECK>
+__device__ __forceinline__ void x3_load(const GemmArgs& g, int64_t row0, int64_t col0, int64_t k0,
+                                        int64_t kend, float (&ra)[TL::A_CHUNKS][8],
+                                        float (&rb)[TL::B_CHUNKS][8]) {
+  const float* __restrict__ A = static_cast<const float*>(g.A);
+  const float* __restrict__ B = static_cast<const float*>(g.B);
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < TL::A_CHUNKS; ++i) {
+    const int c = t + TL::NT * i;
+    const int r = c / (BK / 8), kk = (c % (BK / 8)) * 8;
+    const int64_t gr = row0 + r, gk = k0 + kk;
+    if (!CHECK) {
+      const f4 a0 = *reinterpret_cast<const f4*>(A + gr * g.lda + gk);
+      const f4 a1 = *reinterpret_cast<const f4*>(A + gr * g.lda + gk + 4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        ra[i][e] = a0[e];
+        ra[i][4 + e] = a1[e];
+      }
+    } else {
+      const bool rin = gr < g.m;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ra[i][e] = (rin && gk + e < kend) ? A[gr * g.lda + gk + e] : 0.0f;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TL::B_CHUNKS; ++i) {
+    const int c = t + TL::NT * i;
+    const int col = c % BN, kk = (c / BN) * 8;
+    const int64_t gc = col0 + col, gk = k0 + kk;
+    if (!CHECK) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rb[i][e] = B[(gk + e) * g.ldb + gc];
+    } else {
+      const bool cin = gc < g.n;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rb[i][e] = (cin && gk + e < kend) ? B[(gk + e) * g.ldb + gc] : 0.0f;
+    }
+  }
+}
+
+template <class TL, int BM, int BN, int BK>
+__device__ __forceinline__ void x3_store(unsigned short* stage, const float (&ra)[TL::A_CHUNKS][8],
+                                         const float (&rb)[TL::B_CHUNKS][8]) {
+  unsigned short* a_hi = stage;
+  unsigned short* a_lo = stage + TL::A_PLANE;
+  unsigned short* b_hi = stage + 2 * TL::A_PLANE;
+  unsigned short* b_lo = stage + 2 * TL::A_PLANE + TL::B_PLANE;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < TL::A_CHUNKS; ++i) {
+    const int c = t + TL::NT * i;
+    const int r = c / (BK / 8), kk = (c % (BK / 8)) * 8;
+    us8 hi, lo;
+    split8(ra[i], hi, lo);
+    *reinterpret_cast<us8*>(a_hi + r * TL::LD + kk) = hi;
+    *reinterpret_cast<us8*>(a_lo + r * TL::LD + kk) = lo;
+  }
+#pragma unroll
+  for (int i = 0; i < TL::B_CHUNKS; ++i) {
+    const int c = t + TL::NT * i;
+    const int col = c % BN, kk = (c / BN) * 8;
+    us8 hi, lo;
+    split8(rb[i], hi, lo);
+    *reinterpret_cast<us8*>(b_hi + col * TL::LD + kk) = hi;
+    *reinterpret_cast<us8*>(b_lo + col * TL::LD + kk) = lo;
+  }
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void gemm_bf16x3_kernel(GemmArgs g) {
+  using TL = X3Tile<BM, BN, BK, WM, WN>;
+  __shared__ __attribute__((aligned(16))) unsigned short lds[2][TL::STAGE];
+
+  const int64_t l = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x, g.num_xcds);
+  const ItemCoord ic = item_coord(l, g.tiles_m, g.tiles_n, g.group_m);
+  const int64_t row0 = ic.tile_row * BM, col0 = ic.tile_col * BN;
+  const int64_t kbeg = ic.split * g.k_split;
+  const int64_t kend = min64(g.k, kbeg + g.k_split);
+  const int64_t nk = ceil_div(kend - kbeg, BK);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int lr = lane & 15, lg = lane >> 4;
+  const bool full_mn = (row0 + BM <= g.m) && (col0 + BN <= g.n) && g.vec_a;
+
+  f4 acc[TL::MI][TL::NI];
+#pragma unroll
+  for (int i = 0; i < TL::MI; ++i)
+#pragma unroll
+    for (int j = 0; j < TL::NI; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  float ra[TL::A_CHUNKS][8], rb[TL::B_CHUNKS][8];
+  if (nk > 0) {
+    if (full_mn && kbeg + BK <= kend)
+      x3_load<TL, BM, BN, BK, false>(g, row0, col0, kbeg, kend, ra, rb);
+    else
+      x3_load<TL, BM, BN, BK, true>(g, row0, col0, kbeg, kend, ra, rb);
+    x3_store<TL, BM, BN, BK>(lds[0], ra, rb);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    const bool more = kt + 1 < nk;
+    if (more) {
+      const int64_t k0 = kbeg + (kt + 1) * BK;
+      if (full_mn && k0 + BK <= kend)
+        x3_load<TL, BM, BN, BK, false>(g, row0, col0, k0, kend, ra, rb);
+      else
+        x3_load<TL, BM, BN, BK, true>(g, row0, col0, k0, kend, ra, rb);
+    }
+    const unsigned short* st = lds[cur];
+    const unsigned short* a_hi = st;
+    const unsigned short* a_lo = st + TL::A_PLANE;
+    const unsigned short* b_hi = st + 2 * TL::A_PLANE;
+    const unsigned short* b_lo = st + 2 * TL::A_PLANE + TL::B_PLANE;
+#pragma unroll
+    for (int h = 0; h < BK / 32; ++h) {
+      bf8 ah[TL::MI], al[TL::MI], bh[TL::NI], bl[TL::NI];
+#pragma unroll
+      for (int i = 0; i < TL::MI; ++i) {
+        const int off = (wm * TL::WTM + i * 16 + lr) * TL::LD + h * 32 + lg * 8;
+        ah[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(a_hi + off));
+        al[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(a_lo + off));
+      }
+#pragma unroll
+      for (int j = 0; j < TL::NI; ++j) {
+        const int off = (wn * TL::WTN + j * 16 + lr) * TL::LD + h * 32 + lg * 8;
+        bh[j] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(b_hi + off));
+        bl[j] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(b_lo + off));
+      }
+      // small terms first
+#pragma unroll
+      for (int i = 0; i < TL::MI; ++i)
+#pragma unroll
+        for (int j = 0; j < TL::NI; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    if (more) x3_store<TL, BM, BN, BK>(lds[cur ^ 1], ra, rb);
+    __syncthreads();
+  }
+  f32_epilogue<TL::MI, TL::NI, TL::WTM, TL::WTN>(g, ic, row0, col0, wm, wn, lr, lg, acc);
+}
+
+template <class K>
+hipError_t launch_items(K kernel, int threads, const GemmArgs& g, hipStream_t s) {
+  const int64_t items = g.tiles_m * g.tiles_n * g.splits;
+  if (items <= 0) return hipSuccess;
+  if (items > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)items), dim3(threads), 0, s, g);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm_f32(int tile_id, const GemmArgs& g, hipStream_t s) {
+  switch (tile_id) {
+    case 0: return launch_items(gemm_f32_kernel<128, 128, 32, 2, 2>, 256, g, s);
+    case 1: return launch_items(gemm_f32_kernel<64, 64, 32, 2, 2>, 256, g, s);
+    case 2: return launch_items(gemm_f32_kernel<256, 128, 32, 4, 2>, 512, g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_gemm_bf16x3(int tile_id, const GemmArgs& g, hipStream_t s) {
+  switch (tile_id) {
+    case 0: return launch_items(gemm_bf16x3_kernel<128, 128, 32, 2, 2>, 256, g, s);
+    case 1: return launch_items(gemm_bf16x3_kernel<64, 64, 32, 2, 2>, 256, g, s);
+    case 2: return launch_items(gemm_bf16x3_kernel<256, 128, 32, 4, 2>, 512, g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace cosma

@@ -3,8 +3,6 @@
 #include "ozaki.hpp"
 
 namespace cosma {
-hipError_t launch_gemm_f32(int, const GemmArgs&, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_gemm_bf16x3(int, const GemmArgs&, hipStream_t) { return hipErrorNotSupported; }
 int run_ozaki(const cosma_plan_info&, double, const void*, int64_t, const void*, int64_t, double,
               void*, int64_t, void*, hipStream_t) {
   return COSMA_ERR_UNSUPPORTED;

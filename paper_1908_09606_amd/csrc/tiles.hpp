@@ -31,12 +31,14 @@ constexpr TileDesc kTilesF64[] = {
     {256, 128, 16, 512, 1, 0.92},
 };
 constexpr TileDesc kTilesF32[] = {
-    {128, 128, 32, 256, 2, 0.85},
+    {128, 128, 32, 256, 2, 0.80},
     {64, 64, 32, 256, 4, 0.70},
+    {256, 128, 32, 512, 1, 0.85},
 };
 constexpr TileDesc kTilesBf16x3[] = {
-    {128, 128, 32, 256, 2, 0.60},
-    {64, 64, 32, 256, 4, 0.45},
+    {128, 128, 32, 256, 2, 0.50},
+    {64, 64, 32, 256, 4, 0.35},
+    {256, 128, 32, 512, 1, 0.55},
 };
 constexpr TileDesc kTilesOzaki[] = {
     {128, 128, 64, 256, 2, 0.60},

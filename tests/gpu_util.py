@@ -54,3 +54,22 @@ def sampled_check(C_dev_view, m, n, k, seed, dist, alpha=1.0, beta=0.0, C0_host=
     if bound is not None:
         assert err <= bound, f"normalised error {err:.3e} > bound {bound:.3e}"
     return err
+
+
+def run_gemm(cm, m, n, k, A, lda, B, ldb, C, ldc, alpha=1.0, beta=0.0, plan=None, dtype=0):
+    """cosma_gemm / cosma_gemm_planned through the C ABI with the workspace
+    the plan needs registered; synchronises and returns the status."""
+    import torch
+    if plan is None:
+        rc, ws = cm.cosma_workspace_size(m, n, k, dtype)
+        assert rc == 0
+    else:
+        ws = plan.workspace_bytes
+    if ws:
+        cm.ensure_workspace(ws)
+    if plan is None:
+        rc = cm.cosma_gemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype)
+    else:
+        rc = cm.cosma_gemm_planned(plan, alpha, A, lda, B, ldb, beta, C, ldc)
+    torch.cuda.synchronize()
+    return rc

@@ -1,0 +1,106 @@
+"""Native FP32 and BF16x3 paths on the GPU against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_1908_09606_amd as cm
+from gpu_util import device_matrix, log, run_gemm, sampled_check, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+F32, X3 = cm.COSMA_F32, cm.COSMA_F32_BF16X3
+SHAPES = [(1, 1, 1), (1, 7, 3), (17, 33, 5), (64, 64, 32), (65, 63, 33), (130, 129, 131),
+          (257, 300, 97), (300, 257, 1000), (129, 1, 64), (1, 300, 45)]
+
+
+@pytest.mark.parametrize("dtype,rng_int", [(F32, 8), (X3, 16)])
+@pytest.mark.parametrize("tile", range(3))
+def test_integer_exact_all_tiles_ragged(gpu, dtype, rng_int, tile):
+    """Integer inputs: native FP32 sums stay below 2^24 (exact); for BF16x3
+    integers |x| <= 16 are bf16-representable, so every lo piece is zero and
+    the three-product sum is exact as well."""
+    for (m, n, k) in SHAPES:
+        log(f"{'f32' if dtype == F32 else 'bf16x3'} int tile {tile} {m}x{n}x{k}")
+        lda, ldb, ldc = k + 3, n + 1, n + 2
+        _, A = device_matrix(m, k, 5, synth.STREAM_A, synth.INT_F32, rng_int, ld=lda)
+        _, B = device_matrix(k, n, 5, synth.STREAM_B, synth.INT_F32, rng_int, ld=ldb)
+        _, C = device_matrix(m, n, 5, synth.STREAM_C, synth.INT_F32, rng_int, ld=ldc)
+        rc, plan = cm.cosma_plan_make(m, n, k, dtype, tile, 1)
+        assert rc == 0
+        assert run_gemm(cm, m, n, k, A, lda, B, ldb, C, ldc, plan=plan) == 0
+        Ah = synth.gen(m, k, 5, synth.STREAM_A, synth.INT_F32, rng_int).astype(np.int64)
+        Bh = synth.gen(k, n, 5, synth.STREAM_B, synth.INT_F32, rng_int).astype(np.int64)
+        assert np.array_equal(C.cpu().numpy().astype(np.float64), (Ah @ Bh).astype(np.float64)), (m, n, k)
+
+
+@pytest.mark.parametrize("dtype", [F32, X3])
+def test_split_k_bit_identical_on_integers(gpu, dtype):
+    m, n, k = 300, 200, 3000
+    Ah = synth.gen(m, k, 9, synth.STREAM_A, synth.INT_F32, 8).astype(np.int64)
+    Bh = synth.gen(k, n, 9, synth.STREAM_B, synth.INT_F32, 8).astype(np.int64)
+    exact = (Ah @ Bh).astype(np.float64)
+    _, A = device_matrix(m, k, 9, synth.STREAM_A, synth.INT_F32, 8)
+    _, B = device_matrix(k, n, 9, synth.STREAM_B, synth.INT_F32, 8)
+    for tile in range(3):
+        for pk in (1, 2, 3, 5):
+            log(f"dtype {dtype} split-k tile {tile} pk {pk}")
+            _, C = device_matrix(m, n, 1, synth.STREAM_C, synth.UNIFORM_F32)
+            rc, plan = cm.cosma_plan_make(m, n, k, dtype, tile, pk)
+            assert rc == 0 and plan.p_k == pk
+            assert run_gemm(cm, m, n, k, A, k, B, n, C, n, plan=plan) == 0
+            assert np.array_equal(C.cpu().numpy().astype(np.float64), exact), (tile, pk)
+
+
+@pytest.mark.parametrize("dtype", [F32, X3])
+@pytest.mark.parametrize("k,pk", [(512, 1), (3000, 1), (3000, 3)])
+def test_uniform_within_fp32_bound(gpu, dtype, k, pk):
+    m, n = 333, 270
+    log(f"dtype {dtype} uniform k {k} pk {pk}")
+    _, A = device_matrix(m, k, 2, synth.STREAM_A, synth.UNIFORM_F32)
+    _, B = device_matrix(k, n, 2, synth.STREAM_B, synth.UNIFORM_F32)
+    _, C = device_matrix(m, n, 2, synth.STREAM_C, synth.UNIFORM_F32)
+    C0 = synth.gen(m, n, 2, synth.STREAM_C, synth.UNIFORM_F32)
+    alpha, beta = 0.75, -0.5
+    rc, plan = cm.cosma_plan_make(m, n, k, dtype, 0, pk)
+    assert run_gemm(cm, m, n, k, A, k, B, n, C, n, alpha, beta, plan=plan) == 0
+    ref, D = oracle.gemm(synth.gen(m, k, 2, synth.STREAM_A, synth.UNIFORM_F32),
+                         synth.gen(k, n, 2, synth.STREAM_B, synth.UNIFORM_F32), alpha, beta, C0)
+    err = oracle.normalised_err(C.cpu().numpy(), ref, D)
+    log(f"  err={err:.3e} bound={oracle.fp32_bound(k):.3e}")
+    assert err <= oracle.fp32_bound(k)
+
+
+def test_bf16x3_small_k_reported(gpu):
+    """Below k ~ 110 the dropped bf16 terms (about 3 * 2^-16 relative) can
+    exceed 8k * 2^-24; the error is reported, and must still be far below
+    single-bf16 accuracy."""
+    m, n, k = 128, 128, 16
+    _, A = device_matrix(m, k, 7, synth.STREAM_A, synth.UNIFORM_F32)
+    _, B = device_matrix(k, n, 7, synth.STREAM_B, synth.UNIFORM_F32)
+    _, C = device_matrix(m, n, 7, synth.STREAM_C, synth.UNIFORM_F32)
+    assert run_gemm(cm, m, n, k, A, k, B, n, C, n, dtype=X3) == 0
+    ref, D = oracle.gemm(synth.gen(m, k, 7, synth.STREAM_A, synth.UNIFORM_F32),
+                         synth.gen(k, n, 7, synth.STREAM_B, synth.UNIFORM_F32))
+    err = oracle.normalised_err(C.cpu().numpy(), ref, D)
+    log(f"  bf16x3 k=16 err={err:.3e} (8k*2^-24 = {oracle.fp32_bound(k):.3e})")
+    assert err < 4 * 2.0 ** -16
+
+
+@pytest.mark.parametrize("dtype", [F32, X3])
+def test_blas_quick_returns(gpu, dtype):
+    import torch
+    m, n, k = 70, 90, 33
+    _, A = device_matrix(m, k, 4, synth.STREAM_A, synth.UNIFORM_F32)
+    _, B = device_matrix(k, n, 4, synth.STREAM_B, synth.UNIFORM_F32)
+    _, C = device_matrix(m, n, 4, synth.STREAM_C, synth.UNIFORM_F32)
+    C0 = C.clone()
+    An = A.clone().fill_(float("nan"))
+    assert run_gemm(cm, m, n, k, An, k, B, n, C, n, 0.0, 0.5, dtype=dtype) == 0
+    assert torch.equal(C, 0.5 * C0)
+    C.fill_(float("nan"))
+    assert run_gemm(cm, m, n, k, A, k, B, n, C, n, 1.0, 0.0, dtype=dtype) == 0
+    assert not torch.isnan(C).any().item()
+    C.copy_(C0)
+    assert run_gemm(cm, m, n, 0, A, 1, B, n, C, n, 1.0, 2.0, dtype=dtype) == 0
+    assert torch.equal(C, 2.0 * C0)

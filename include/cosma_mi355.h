@@ -157,6 +157,10 @@ COSMA_API int cosma_plan_query_facts(int64_t m, int64_t n, int64_t k, int dtype,
 /* Plan with a forced tile (menu index) and split factor p_k >= 1. */
 COSMA_API int cosma_plan_make(int64_t m, int64_t n, int64_t k, int dtype, int tile_id, int p_k,
                     cosma_plan_info* out);
+/* Ozaki plans: set the number of int8 digit slices per operand (1..8) and
+   recompute the plan's workspace.  More slices cost s(s+1)/2 int8 products
+   and shrink the truncation error by 2^-7 per slice. */
+COSMA_API int cosma_plan_set_slices(cosma_plan_info* plan, int slices);
 /* Number of kernel tiles for dtype, and the shape of tile `id`. */
 COSMA_API int cosma_tile_count(int dtype);
 COSMA_API int cosma_tile_shape(int dtype, int id, int32_t* tile_m, int32_t* tile_n, int32_t* tile_k);

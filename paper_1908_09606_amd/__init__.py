@@ -33,7 +33,7 @@ COSMA_ERR_NO_MEMORY = -5
 EXPORTED = [
     "cosma_gemm", "cosma_gemm_planned", "cosma_gemm_batched", "cosma_batch_create",
     "cosma_batch_run", "cosma_batch_destroy", "cosma_plan_query", "cosma_plan_query_facts",
-    "cosma_plan_make", "cosma_tile_count", "cosma_tile_shape", "cosma_device_query",
+    "cosma_plan_make", "cosma_plan_set_slices", "cosma_tile_count", "cosma_tile_shape", "cosma_device_query",
     "cosma_thm1_bound", "cosma_seq_schedule", "cosma_par_schedule", "cosma_fit_ranks",
     "cosma_io_count", "cosma_workspace_size", "cosma_set_workspace", "cosma_status_string",
     "cosma_version",
@@ -104,6 +104,7 @@ def lib():
                 "cosma_plan_query_facts": (i32, [i64, i64, i64, i32,
                                                  ctypes.POINTER(cosma_device_facts), dbl, P]),
                 "cosma_plan_make": (i32, [i64, i64, i64, i32, i32, i32, P]),
+                "cosma_plan_set_slices": (i32, [P, i32]),
                 "cosma_tile_count": (i32, [i32]),
                 "cosma_tile_shape": (i32, [i32, i32, ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int32),
@@ -228,6 +229,10 @@ def cosma_plan_make(m, n, k, dtype, tile_id, p_k):
     p = cosma_plan_info()
     rc = lib().cosma_plan_make(m, n, k, _dtype(dtype), tile_id, p_k, ctypes.byref(p))
     return rc, p
+
+
+def cosma_plan_set_slices(plan, slices) -> int:
+    return lib().cosma_plan_set_slices(ctypes.byref(plan), int(slices))
 
 
 def cosma_tile_count(dtype) -> int:

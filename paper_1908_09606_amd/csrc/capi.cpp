@@ -294,6 +294,13 @@ int cosma_plan_make(int64_t m, int64_t n, int64_t k, int dtype, int tile_id, int
   return COSMA_OK;
 }
 
+int cosma_plan_set_slices(cosma_plan_info* plan, int slices) {
+  if (!plan || plan->dtype != F64_OZAKI_I8 || slices < 1 || slices > 8) return COSMA_ERR_INVALID_ARG;
+  plan->slices = slices;
+  plan->workspace_bytes = workspace_bytes(*plan);
+  return COSMA_OK;
+}
+
 int cosma_tile_count(int dtype) {
   int c = 0;
   tile_menu(dtype, &c);

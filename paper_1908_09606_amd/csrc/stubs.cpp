@@ -3,10 +3,6 @@
 #include "ozaki.hpp"
 
 namespace cosma {
-int run_ozaki(const cosma_plan_info&, double, const void*, int64_t, const void*, int64_t, double,
-              void*, int64_t, void*, hipStream_t) {
-  return COSMA_ERR_UNSUPPORTED;
-}
 }  // namespace cosma
 
 extern "C" {

@@ -41,8 +41,7 @@ constexpr TileDesc kTilesBf16x3[] = {
     {256, 128, 32, 512, 1, 0.55},
 };
 constexpr TileDesc kTilesOzaki[] = {
-    {128, 128, 64, 256, 2, 0.60},
-    {64, 64, 64, 256, 4, 0.45},
+    {64, 64, 64, 256, 1, 0.45},
 };
 
 COSMA_HD inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

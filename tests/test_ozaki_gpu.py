@@ -1,0 +1,146 @@
+"""Ozaki INT8-slice path (FP64-accurate) on the GPU against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_1908_09606_amd as cm
+from gpu_util import device_matrix, log, run_gemm, sampled_check, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+OZ = cm.COSMA_F64_OZAKI_I8
+SHAPES = [(1, 1, 1), (1, 7, 3), (17, 33, 5), (64, 64, 64), (65, 63, 65), (130, 129, 131),
+          (257, 300, 97), (300, 257, 1000), (129, 1, 64), (1, 300, 45)]
+
+
+def oz_plan(m, n, k, slices, p_k=1):
+    rc, plan = cm.cosma_plan_make(m, n, k, OZ, 0, p_k)
+    assert rc == 0
+    assert cm.cosma_plan_set_slices(plan, slices) == 0
+    return plan
+
+
+@pytest.mark.parametrize("slices", [1, 2, 7])
+def test_integer_single_digit_exact(gpu, slices):
+    """|x| <= 127 integers need one digit after row/column scaling, so the
+    slice products are the exact integer product for every s."""
+    for (m, n, k) in SHAPES:
+        log(f"ozaki s={slices} int {m}x{n}x{k}")
+        lda, ldb, ldc = k + 3, n + 1, n + 2
+        _, A = device_matrix(m, k, 5, synth.STREAM_A, synth.INT_F64, 127, ld=lda)
+        _, B = device_matrix(k, n, 5, synth.STREAM_B, synth.INT_F64, 127, ld=ldb)
+        _, C = device_matrix(m, n, 5, synth.STREAM_C, synth.INT_F64, 127, ld=ldc)
+        plan = oz_plan(m, n, k, slices)
+        assert run_gemm(cm, m, n, k, A, lda, B, ldb, C, ldc, plan=plan) == 0
+        Ah = synth.gen(m, k, 5, synth.STREAM_A, synth.INT_F64, 127).astype(np.int64)
+        Bh = synth.gen(k, n, 5, synth.STREAM_B, synth.INT_F64, 127).astype(np.int64)
+        assert np.array_equal(C.cpu().numpy(), (Ah @ Bh).astype(np.float64)), (m, n, k)
+
+
+def test_two_digit_times_one_digit_exact_with_two_slices(gpu):
+    """A with 14-bit integers needs two digits, B with 7-bit integers one: with
+    s = 2 the triangular truncation (u + v <= 3) drops only zero products, so
+    the result is exact (error-free transformation)."""
+    m, n, k = 190, 150, 700
+    _, A = device_matrix(m, k, 8, synth.STREAM_A, synth.INT_F64, 16383)
+    _, B = device_matrix(k, n, 8, synth.STREAM_B, synth.INT_F64, 127)
+    _, C = device_matrix(m, n, 8, synth.STREAM_C, synth.UNIFORM_F64)
+    plan = oz_plan(m, n, k, 2)
+    assert run_gemm(cm, m, n, k, A, k, B, n, C, n, plan=plan) == 0
+    Ah = synth.gen(m, k, 8, synth.STREAM_A, synth.INT_F64, 16383).astype(np.int64)
+    Bh = synth.gen(k, n, 8, synth.STREAM_B, synth.INT_F64, 127).astype(np.int64)
+    assert np.array_equal(C.cpu().numpy(), (Ah @ Bh).astype(np.float64))
+    # with one slice the second digit of A is dropped: the result must differ
+    plan1 = oz_plan(m, n, k, 1)
+    assert run_gemm(cm, m, n, k, A, k, B, n, C, n, plan=plan1) == 0
+    assert not np.array_equal(C.cpu().numpy(), (Ah @ Bh).astype(np.float64))
+
+
+def test_split_k_bit_identical_on_integers(gpu):
+    m, n, k = 200, 190, 3000
+    Ah = synth.gen(m, k, 9, synth.STREAM_A, synth.INT_F64, 127).astype(np.int64)
+    Bh = synth.gen(k, n, 9, synth.STREAM_B, synth.INT_F64, 127).astype(np.int64)
+    exact = (Ah @ Bh).astype(np.float64)
+    _, A = device_matrix(m, k, 9, synth.STREAM_A, synth.INT_F64, 127)
+    _, B = device_matrix(k, n, 9, synth.STREAM_B, synth.INT_F64, 127)
+    for pk in (1, 2, 3, 5):
+        _, C = device_matrix(m, n, 1, synth.STREAM_C, synth.UNIFORM_F64)
+        plan = oz_plan(m, n, k, 3, pk)
+        assert plan.p_k == pk
+        assert run_gemm(cm, m, n, k, A, k, B, n, C, n, plan=plan) == 0
+        assert np.array_equal(C.cpu().numpy(), exact), pk
+
+
+@pytest.mark.parametrize("slices", [6, 7, 8])
+def test_wide_exponent_data_error(gpu, slices):
+    """Entries sign * U[1,2) * 2^e, e in [-20, 20]; s = 7 and 8 must meet
+    4k * 2^-53 (s = 6 is reported)."""
+    m, n, k = 300, 280, 2048
+    _, A = device_matrix(m, k, 4, synth.STREAM_A, synth.WIDE_F64)
+    _, B = device_matrix(k, n, 4, synth.STREAM_B, synth.WIDE_F64)
+    _, C = device_matrix(m, n, 4, synth.STREAM_C, synth.UNIFORM_F64)
+    C0 = synth.gen(m, n, 4, synth.STREAM_C, synth.UNIFORM_F64)
+    alpha, beta = 1.5, -0.25
+    plan = oz_plan(m, n, k, slices)
+    assert run_gemm(cm, m, n, k, A, k, B, n, C, n, alpha, beta, plan=plan) == 0
+    ref, D = oracle.gemm(synth.gen(m, k, 4, synth.STREAM_A, synth.WIDE_F64),
+                         synth.gen(k, n, 4, synth.STREAM_B, synth.WIDE_F64), alpha, beta, C0)
+    err = oracle.normalised_err(C.cpu().numpy(), ref, D)
+    log(f"  ozaki s={slices} err={err:.3e} bound={oracle.fp64_bound(k):.3e}")
+    if slices >= 7:
+        assert err <= oracle.fp64_bound(k)
+    else:
+        assert err < 1e-9
+
+
+def test_zero_rows_and_columns(gpu):
+    """An all-zero row of A / column of B gets exponent 0 and zero digits:
+    its row / column of C is exactly zero and the rest stays exact."""
+    import torch
+    m, n, k = 70, 80, 90
+    _, A = device_matrix(m, k, 3, synth.STREAM_A, synth.INT_F64, 127)
+    _, B = device_matrix(k, n, 3, synth.STREAM_B, synth.INT_F64, 127)
+    A[5].zero_()
+    B[:, 7].zero_()
+    C = torch.full((m, n), float("nan"), dtype=torch.float64, device="cuda")
+    assert run_gemm(cm, m, n, k, A, k, B, n, C, n, dtype=OZ) == 0
+    Ah, Bh = A.cpu().numpy().astype(np.int64), B.cpu().numpy().astype(np.int64)
+    Ch = C.cpu().numpy()
+    assert np.all(Ch[5] == 0.0) and np.all(Ch[:, 7] == 0.0)
+    assert np.array_equal(Ch, (Ah @ Bh).astype(np.float64))
+
+
+def test_small_k_wide_exponents_reported(gpu):
+    """With 41 binades of exponent spread and few terms, D_ij can lie far
+    below 2^(e_i + f_j), and the 7s-bit truncation relative to the row and
+    column maxima shows: at k = 90 even s = 8 does not meet 4k * 2^-53.  The
+    error is reported and must shrink by about 2^-7 per extra slice."""
+    m, n, k = 70, 80, 90
+    _, A = device_matrix(m, k, 3, synth.STREAM_A, synth.WIDE_F64)
+    _, B = device_matrix(k, n, 3, synth.STREAM_B, synth.WIDE_F64)
+    ref, D = oracle.gemm(synth.gen(m, k, 3, synth.STREAM_A, synth.WIDE_F64),
+                         synth.gen(k, n, 3, synth.STREAM_B, synth.WIDE_F64))
+    errs = {}
+    for s in (6, 7, 8):
+        _, C = device_matrix(m, n, 3, synth.STREAM_C, synth.UNIFORM_F64)
+        assert run_gemm(cm, m, n, k, A, k, B, n, C, n, plan=oz_plan(m, n, k, s)) == 0
+        errs[s] = oracle.normalised_err(C.cpu().numpy(), ref, D)
+    log(f"  k=90 wide exponents: errors by slices {errs}, 4k*2^-53 = {oracle.fp64_bound(k):.2e}")
+    assert errs[8] < errs[7] < errs[6] < 1e-6
+    assert errs[7] / errs[8] > 16 and errs[6] / errs[7] > 16
+
+
+def test_blas_quick_returns(gpu):
+    import torch
+    m, n, k = 70, 90, 33
+    _, A = device_matrix(m, k, 4, synth.STREAM_A, synth.UNIFORM_F64)
+    _, B = device_matrix(k, n, 4, synth.STREAM_B, synth.UNIFORM_F64)
+    _, C = device_matrix(m, n, 4, synth.STREAM_C, synth.UNIFORM_F64)
+    C0 = C.clone()
+    An = A.clone().fill_(float("nan"))
+    assert run_gemm(cm, m, n, k, An, k, B, n, C, n, 0.0, 0.5, dtype=OZ) == 0
+    assert torch.equal(C, 0.5 * C0)
+    C.copy_(C0)
+    assert run_gemm(cm, m, n, 0, A, 1, B, n, C, n, 1.0, 2.0, dtype=OZ) == 0
+    assert torch.equal(C, 2.0 * C0)

@@ -182,11 +182,13 @@ def main():
         out["copy_calibration_bytes"] = nel * 8
         del src, dst
 
+    keep = []
     if not args.no_variants:
-        out["variants"] = run_variants(torch, cm, synth, dev, stream)
+        out["variants"] = run_variants(torch, cm, synth, dev, stream, keep)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(probs, torch)
+        out["accuracy"] = sampled_accuracy(probs, keep)
 
     # release inputs before printing
     for p in probs:
@@ -194,9 +196,115 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def run_variants(torch, cm, synth, dev, stream):
-    """Precision and batching variants, each on its own workload."""
-    return {}
+def _time(torch, stream, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def run_variants(torch, cm, synth, dev, stream, keep):
+    """Precision and batching variants, each on its own workload:
+    BF16x3 vs native FP32 (16384^3 and 4096^2 x 2^18, uniform FP32),
+    Ozaki INT8 slices vs native FP64 (8192^3, sign*U[1,2)*2^e, e in [-20,20]),
+    512 uneven FP32 products: one graph launch vs 512 single launches.
+    Results needed for the accuracy check are appended to `keep`."""
+    out = {}
+    rows = []
+    for (m, n, k) in ((16384, 16384, 16384), (4096, 4096, 1 << 18)):
+        A = torch.empty((m, k), dtype=torch.float32, device=dev)
+        B = torch.empty((k, n), dtype=torch.float32, device=dev)
+        synth.fill_device(A, SEED, synth.STREAM_A, synth.UNIFORM_F32)
+        synth.fill_device(B, SEED, synth.STREAM_B, synth.UNIFORM_F32)
+        res = {}
+        for dt in ("f32", "bf16x3"):
+            C = torch.empty((m, n), dtype=torch.float32, device=dev)
+            rc, plan = cm.cosma_plan_query(m, n, k, dt)
+            cm.ensure_workspace(plan.workspace_bytes)
+            ms = _time(torch, stream, lambda: cm.gemm(A, B, C, dtype=dt, stream=stream), 3)
+            res[dt] = (ms, 2.0 * m * n * k / (ms * 1e-3) / 1e12, plan)
+            keep.append((f"{dt} {m}x{n}x{k}", C, m, n, k, synth.UNIFORM_F32, "f32"))
+        f32, x3 = res["f32"], res["bf16x3"]
+        rows.append({"shape": f"{m}x{n}x{k}", "f32_ms": round(f32[0], 3),
+                     "f32_tflops": round(f32[1], 2), "f32_frac_peak": round(f32[1] / PEAK_F32, 4),
+                     "bf16x3_ms": round(x3[0], 3), "bf16x3_tflops": round(x3[1], 2),
+                     "bf16x3_frac_bf16_peak": round(3 * x3[1] / PEAK_BF16, 4),
+                     "bf16x3_tile": f"{x3[2].tile_m}x{x3[2].tile_n}",
+                     "speedup_vs_f32": round(f32[0] / x3[0], 3)})
+        del A, B
+    out["bf16x3_vs_f32"] = rows
+
+    m = n = k = 8192
+    A = torch.empty((m, k), dtype=torch.float64, device=dev)
+    B = torch.empty((k, n), dtype=torch.float64, device=dev)
+    synth.fill_device(A, SEED, synth.STREAM_A, synth.WIDE_F64)
+    synth.fill_device(B, SEED, synth.STREAM_B, synth.WIDE_F64)
+    res = {}
+    for dt in ("f64", "ozaki"):
+        C = torch.empty((m, n), dtype=torch.float64, device=dev)
+        rc, plan = cm.cosma_plan_query(m, n, k, dt)
+        cm.ensure_workspace(plan.workspace_bytes)
+        ms = _time(torch, stream, lambda: cm.gemm(A, B, C, dtype=dt, stream=stream), 5)
+        res[dt] = (ms, 2.0 * m * n * k / (ms * 1e-3) / 1e12, plan)
+        keep.append((f"{dt} {m}^3 wide", C, m, n, k, synth.WIDE_F64, "f64"))
+    s_ = res["ozaki"][2].slices
+    out["ozaki_vs_f64"] = {
+        "shape": "8192^3, sign*U[1,2)*2^e, e in [-20,20]", "slices": s_,
+        "int8_products": s_ * (s_ + 1) // 2,
+        "f64_ms": round(res["f64"][0], 3), "f64_tflops": round(res["f64"][1], 2),
+        "ozaki_ms": round(res["ozaki"][0], 3), "ozaki_tflops": round(res["ozaki"][1], 2),
+        "ozaki_frac_int8_peak": round(res["ozaki"][1] * s_ * (s_ + 1) / 2 / PEAK_I8, 4),
+        "speedup_vs_f64": round(res["f64"][0] / res["ozaki"][0], 3)}
+    del A, B
+
+    dims = [tuple(int(x) for x in d) for d in synth.batch_dims(512, seed=5)]
+    flops = sum(2.0 * a * b * c for a, b, c in dims)
+    mats = []
+    for i, (bm, bn, bk) in enumerate(dims):
+        A = torch.empty((bm, bk), dtype=torch.float32, device=dev)
+        B = torch.empty((bk, bn), dtype=torch.float32, device=dev)
+        C = torch.empty((bm, bn), dtype=torch.float32, device=dev)
+        synth.fill_device(A, 1000 + i, synth.STREAM_A, synth.UNIFORM_F32)
+        synth.fill_device(B, 1000 + i, synth.STREAM_B, synth.UNIFORM_F32)
+        mats.append((A, B, C))
+    args = (512, [d[0] for d in dims], [d[1] for d in dims], [d[2] for d in dims], [1.0] * 512,
+            [x[0] for x in mats], [d[2] for d in dims], [x[1] for x in mats],
+            [d[1] for d in dims], [0.0] * 512, [x[2] for x in mats], [d[1] for d in dims])
+    rc, h = cm.cosma_batch_create(*args, cm.COSMA_F32, stream)
+    cm.check(rc, "cosma_batch_create")
+    rc, policy, groups, items, pol_ms = cm.cosma_batch_info(h)
+    t_graph = _time(torch, stream, lambda: cm.cosma_batch_run(h, stream), 5)
+    ws = max(cm.cosma_workspace_size(a, b, c, cm.COSMA_F32)[1] for a, b, c in dims)
+    cm.ensure_workspace(ws)
+
+    def loop():
+        for i, (bm, bn, bk) in enumerate(dims):
+            cm.cosma_gemm(bm, bn, bk, 1.0, mats[i][0], bk, mats[i][1], bn, 0.0, mats[i][2], bn,
+                          cm.COSMA_F32, stream)
+    t_loop = _time(torch, stream, loop, 3)
+    cm.cosma_batch_run(h, stream)  # final results come from the graph
+    torch.cuda.synchronize()
+    cm.cosma_batch_destroy(h)
+    out["batched_512_f32"] = {
+        "problems": 512, "dims": "m,n,k log-uniform in [64,4096], seeded per problem",
+        "sum_2mnk": flops, "graph_ms": round(t_graph, 3),
+        "graph_tflops": round(flops / (t_graph * 1e-3) / 1e12, 2),
+        "loop_of_single_launches_ms": round(t_loop, 3),
+        "loop_tflops": round(flops / (t_loop * 1e-3) / 1e12, 2),
+        "speedup_vs_loop": round(t_loop / t_graph, 3), "autotuned_policy": policy,
+        "policy_candidates_ms": [round(x, 3) for x in pol_ms], "persistent_launches": groups,
+        "work_items": items}
+    keep.append(("batched", mats, dims, None, None, synth.UNIFORM_F32, "f32"))
+    return out
 
 
 def cpu_baseline(probs, torch):
@@ -225,6 +333,49 @@ def cpu_baseline(probs, torch):
                       f"({flops:.3e} flops, {dt:.2f} s)",
             "gpu_err_on_sample": err, "err_bound": oracle.fp64_bound(k),
             "within_bound": bool(err <= oracle.fp64_bound(k))}
+
+
+def sampled_accuracy(probs, keep):
+    """Normalised error of every measured result on sampled rows and columns
+    (random ones plus the last), against the oracle on regenerated inputs."""
+    import numpy as np
+    import oracle
+    import synth
+    rng = np.random.default_rng(7)
+    out = []
+
+    def one(name, C, m, n, k, seed, dist, cls, nsamp=12):
+        rows = np.unique(np.concatenate([rng.integers(0, m, nsamp), [0, m - 1]]))
+        cols = np.unique(np.concatenate([rng.integers(0, n, nsamp), [0, n - 1]]))
+        Ar = synth.gen(m, k, seed, synth.STREAM_A, dist, row_idx=rows)
+        Bc = synth.gen(k, n, seed, synth.STREAM_B, dist, col_idx=cols)
+        ref, D = oracle.gemm(Ar, Bc)
+        import torch
+        ri = torch.as_tensor(rows, device=C.device)
+        ci = torch.as_tensor(cols, device=C.device)
+        got = C.index_select(0, ri).index_select(1, ci).double().cpu().numpy()
+        err = oracle.normalised_err(got, ref, D)
+        bound = oracle.fp64_bound(k) if cls == "f64" else oracle.fp32_bound(k)
+        return {"result": name, "err": err, "bound": bound, "within": bool(err <= bound)}
+
+    for p in probs:
+        out.append(one(f"f64 {p['name']}", p["C"], p["m"], p["n"], p["k"], SEED,
+                       synth.UNIFORM_F64, "f64", 8 if p["k"] > 100000 else 16))
+    for entry in keep:
+        if entry[0] == "batched":
+            _, mats, dims, _, _, dist, cls = entry
+            worst = None
+            for i in range(0, len(dims), 8):
+                m, n, k = dims[i]
+                r = one(f"batched #{i}", mats[i][2], m, n, k, 1000 + i, dist, cls, 2)
+                if worst is None or r["err"] / r["bound"] > worst["err"] / worst["bound"]:
+                    worst = r
+            worst["result"] = "batched 512 (every 8th problem, worst)"
+            out.append(worst)
+        else:
+            name, C, m, n, k, dist, cls = entry
+            out.append(one(name, C, m, n, k, SEED, dist, cls, 8 if k > 100000 else 12))
+    return out
 
 
 if __name__ == "__main__":

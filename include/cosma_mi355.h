@@ -143,7 +143,19 @@ COSMA_API int cosma_batch_create(int64_t count, const int64_t* m, const int64_t*
                        void* const* C, const int64_t* ldc, int dtype, void* stream,
                        void** handle);
 COSMA_API int cosma_batch_run(void* handle, void* stream);
+/* Waits for the device, then frees the handle's work list and graph. */
 COSMA_API int cosma_batch_destroy(void* handle);
+/* Tile policy the autotuner kept (0 = the planner's per-problem choice,
+   1 = all 64x64, 2 = all 128x128, 3 = size threshold), number of persistent
+   launches (one per tile variant), work items, and the timed milliseconds
+   of each candidate policy (0 when tuning was skipped: some beta != 0, or
+   COSMA_AUTOTUNE=0). */
+COSMA_API int cosma_batch_info(void* handle, int* policy, int* groups, int64_t* items,
+                               double* policy_ms, int policy_ms_len);
+/* Tile id (menu index of the batch's dtype) each input problem runs with, or
+   -1 for problems without products (m, n or k zero, or alpha zero); count
+   must equal the count given at creation. */
+COSMA_API int cosma_batch_tiles(void* handle, int64_t count, int32_t* tile_ids);
 
 /* ---- planner (host only; no GPU needed) --------------------------------- */
 

@@ -32,7 +32,7 @@ COSMA_ERR_NO_MEMORY = -5
 
 EXPORTED = [
     "cosma_gemm", "cosma_gemm_planned", "cosma_gemm_batched", "cosma_batch_create",
-    "cosma_batch_run", "cosma_batch_destroy", "cosma_plan_query", "cosma_plan_query_facts",
+    "cosma_batch_run", "cosma_batch_destroy", "cosma_batch_info", "cosma_batch_tiles", "cosma_plan_query", "cosma_plan_query_facts",
     "cosma_plan_make", "cosma_plan_set_slices", "cosma_tile_count", "cosma_tile_shape", "cosma_device_query",
     "cosma_thm1_bound", "cosma_seq_schedule", "cosma_par_schedule", "cosma_fit_ranks",
     "cosma_io_count", "cosma_workspace_size", "cosma_set_workspace", "cosma_status_string",
@@ -100,6 +100,9 @@ def lib():
                                              pdbl, ppv, pi64, i32, vp, ctypes.POINTER(vp)]),
                 "cosma_batch_run": (i32, [vp, vp]),
                 "cosma_batch_destroy": (i32, [vp]),
+                "cosma_batch_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), pi64,
+                                           pdbl, i32]),
+                "cosma_batch_tiles": (i32, [vp, i64, ctypes.POINTER(ctypes.c_int32)]),
                 "cosma_plan_query": (i32, [i64, i64, i64, i32, P]),
                 "cosma_plan_query_facts": (i32, [i64, i64, i64, i32,
                                                  ctypes.POINTER(cosma_device_facts), dbl, P]),
@@ -209,6 +212,22 @@ def cosma_batch_run(handle, stream=None) -> int:
 
 def cosma_batch_destroy(handle) -> int:
     return lib().cosma_batch_destroy(handle)
+
+
+def cosma_batch_info(handle):
+    """Returns (status, policy, groups, items, [ms per candidate policy])."""
+    pol, groups, items = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+    ms = (ctypes.c_double * 4)()
+    rc = lib().cosma_batch_info(handle, ctypes.byref(pol), ctypes.byref(groups),
+                                ctypes.byref(items), ms, 4)
+    return rc, pol.value, groups.value, items.value, list(ms)
+
+
+def cosma_batch_tiles(handle, count):
+    """Returns (status, [tile id per input problem])."""
+    out = (ctypes.c_int32 * max(1, count))()
+    rc = lib().cosma_batch_tiles(handle, count, out)
+    return rc, list(out)[:count]
 
 
 def cosma_plan_query(m, n, k, dtype):

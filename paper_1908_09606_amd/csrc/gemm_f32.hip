@@ -138,14 +138,13 @@ __device__ __forceinline__ void f32_epilogue(const GemmArgs& g, const ItemCoord&
   }
 }
 
+// One work item: the BM x BN block (ic.tile_row, ic.tile_col) over the
+// reduction range of split ic.split.  As / Bs: two LDS stages each.
 template <int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(WM* WN * 64) void gemm_f32_kernel(GemmArgs g) {
+__device__ __forceinline__ void f32_tile(const GemmArgs& g, const ItemCoord& ic,
+                                         float (*As)[F32Tile<BM, BN, BK, WM, WN>::A_STAGE],
+                                         float (*Bs)[F32Tile<BM, BN, BK, WM, WN>::B_STAGE]) {
   using TL = F32Tile<BM, BN, BK, WM, WN>;
-  __shared__ __attribute__((aligned(16))) float As[2][TL::A_STAGE];
-  __shared__ __attribute__((aligned(16))) float Bs[2][TL::B_STAGE];
-
-  const int64_t l = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x, g.num_xcds);
-  const ItemCoord ic = item_coord(l, g.tiles_m, g.tiles_n, g.group_m);
   const int64_t row0 = ic.tile_row * BM, col0 = ic.tile_col * BN;
   const int64_t kbeg = ic.split * g.k_split;
   const int64_t kend = min64(g.k, kbeg + g.k_split);
@@ -207,6 +206,50 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_f32_kernel(GemmArgs g) {
     __syncthreads();
   }
   f32_epilogue<TL::MI, TL::NI, TL::WTM, TL::WTN>(g, ic, row0, col0, wm, wn, lr, lg, acc);
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void gemm_f32_kernel(GemmArgs g) {
+  using TL = F32Tile<BM, BN, BK, WM, WN>;
+  __shared__ __attribute__((aligned(16))) float As[2][TL::A_STAGE];
+  __shared__ __attribute__((aligned(16))) float Bs[2][TL::B_STAGE];
+  const int64_t l = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x, g.num_xcds);
+  const ItemCoord ic = item_coord(l, g.tiles_m, g.tiles_n, g.group_m);
+  f32_tile<BM, BN, BK, WM, WN>(g, ic, As, Bs);
+}
+
+// Persistent batched form: every workgroup takes (problem, tile) items from
+// the device counter until the list is exhausted; each item is computed
+// exactly as by gemm_f32_kernel with one split.
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void gemm_f32_batched_kernel(BatchArgs b) {
+  using TL = F32Tile<BM, BN, BK, WM, WN>;
+  __shared__ __attribute__((aligned(16))) float As[2][TL::A_STAGE];
+  __shared__ __attribute__((aligned(16))) float Bs[2][TL::B_STAGE];
+  __shared__ unsigned next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(b.counter, 1u);
+    __syncthreads();
+    const unsigned it = next;
+    __syncthreads();
+    if ((int64_t)it >= b.count) return;
+    const BatchItem item = b.items[it];
+    const BatchProblem& p = b.probs[item.problem];
+    GemmArgs g;
+    g.A = p.A; g.B = p.B; g.C = p.C; g.P = nullptr;
+    g.lda = p.lda; g.ldb = p.ldb; g.ldc = p.ldc;
+    g.m = p.m; g.n = p.n; g.k = p.k;
+    g.k_split = p.k; g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.splits = 1;
+    g.ldp = 0; g.split_stride = 0;
+    g.alpha = p.alpha; g.beta = p.beta;
+    g.group_m = 1; g.num_xcds = 1;
+    g.vec_a = p.vec_a; g.vec_b = p.vec_b;
+    ItemCoord ic;
+    ic.split = 0;
+    ic.tile_row = item.tile / p.tiles_n;
+    ic.tile_col = item.tile - ic.tile_row * p.tiles_n;
+    f32_tile<BM, BN, BK, WM, WN>(g, ic, As, Bs);
+  }
 }
 
 // ------------------------------------------------------------- BF16x3
@@ -406,6 +449,38 @@ hipError_t launch_gemm_f32(int tile_id, const GemmArgs& g, hipStream_t s) {
     case 1: return launch_items(gemm_f32_kernel<64, 64, 32, 2, 2>, 256, g, s);
     case 2: return launch_items(gemm_f32_kernel<256, 128, 32, 4, 2>, 512, g, s);
     default: return hipErrorInvalidValue;
+  }
+}
+
+template <class K>
+hipError_t launch_persistent(K kernel, int threads, const BatchArgs& b, int grid, hipStream_t s) {
+  if (b.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(threads), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_f32(int tile_id, const BatchArgs& b, int grid, hipStream_t s) {
+  switch (tile_id) {
+    case 0: return launch_persistent(gemm_f32_batched_kernel<128, 128, 32, 2, 2>, 256, b, grid, s);
+    case 1: return launch_persistent(gemm_f32_batched_kernel<64, 64, 32, 2, 2>, 256, b, grid, s);
+    case 2: return launch_persistent(gemm_f32_batched_kernel<256, 128, 32, 4, 2>, 512, b, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <class K>
+int occupancy_of(K kernel, int threads) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess) return 1;
+  return n < 1 ? 1 : n;
+}
+
+int batched_occupancy_f32(int tile_id) {
+  switch (tile_id) {
+    case 0: return occupancy_of(gemm_f32_batched_kernel<128, 128, 32, 2, 2>, 256);
+    case 1: return occupancy_of(gemm_f32_batched_kernel<64, 64, 32, 2, 2>, 256);
+    case 2: return occupancy_of(gemm_f32_batched_kernel<256, 128, 32, 4, 2>, 512);
+    default: return 1;
   }
 }
 

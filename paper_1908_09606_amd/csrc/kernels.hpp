@@ -26,12 +26,45 @@ struct GemmArgs {
   int vec_a, vec_b;      // operand rows may be read 16 bytes at a time
 };
 
+// Batches: problem descriptors and (problem, tile) work items in device
+// memory; a persistent launch pulls items from a device counter.
+struct BatchProblem {
+  const void* A;
+  const void* B;
+  void* C;
+  int64_t lda, ldb, ldc;
+  int64_t m, n, k;
+  int64_t tiles_m, tiles_n;
+  double alpha, beta;
+  int32_t vec_a, vec_b;
+};
+
+struct BatchItem {
+  int32_t problem;
+  int32_t tile;  // row-major tile index within the problem
+};
+
+struct BatchArgs {
+  const BatchProblem* probs;
+  const BatchItem* items;
+  int64_t count;       // items in this launch
+  unsigned* counter;   // next item to hand out (reset before the launch)
+};
+
 // FP64 MFMA GEMM (tile menu kTilesF64).
 hipError_t launch_gemm_f64(int tile_id, const GemmArgs& g, hipStream_t s);
 // FP32 MFMA GEMM (tile menu kTilesF32).
 hipError_t launch_gemm_f32(int tile_id, const GemmArgs& g, hipStream_t s);
 // FP32-accurate GEMM from three bf16 products (tile menu kTilesBf16x3).
 hipError_t launch_gemm_bf16x3(int tile_id, const GemmArgs& g, hipStream_t s);
+
+// Persistent batched launches (grid = resident workgroups) for a tile variant.
+hipError_t launch_batched_f64(int tile_id, const BatchArgs& b, int grid, hipStream_t s);
+hipError_t launch_batched_f32(int tile_id, const BatchArgs& b, int grid, hipStream_t s);
+// counter[0..n) = 0 with a kernel (graph-capture safe).
+hipError_t launch_reset_counters(unsigned* counter, int n, hipStream_t s);
+// Resident workgroups per CU of a tile variant (from the compiled kernel).
+int batched_occupancy(int dtype, int tile_id);
 
 // C = alpha * sum_{s < splits} P[s] + beta * C, summed in ascending s.
 hipError_t launch_splitk_reduce_f64(const double* P, int64_t split_stride, int64_t ldp,

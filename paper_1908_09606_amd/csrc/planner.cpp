@@ -190,6 +190,26 @@ double q_ea_bytes(int64_t m, int64_t n, int64_t k, int64_t k_split, int64_t spli
   return bytes;
 }
 
+// Cost of one problem inside a persistent batch, where items of many
+// problems share the machine and per-problem wave quantisation does not
+// matter: the padded work of the tile at its expected issue rate against the
+// tile's CU-level I/O (section 5's counted loads) at the memory rate.
+double batch_item_cost(int64_t m, int64_t n, int64_t k, int dtype, int tile_id,
+                       const cosma_device_facts& f) {
+  int cnt = 0;
+  const TileDesc* menu = tile_menu(dtype, &cnt);
+  if (!menu || tile_id < 0 || tile_id >= cnt) return INFINITY;
+  const TileDesc& T = menu[tile_id];
+  const double padded = 2.0 * (double)(ceil_div(m, T.tm) * T.tm) *
+                        (double)(ceil_div(n, T.tn) * T.tn) * (double)k;
+  const double rate = useful_flops_per_clk_per_cu(dtype, ozaki_slices()) * f.clock_ghz * 1e9 *
+                      (double)f.num_cus;
+  const double t_compute = padded / (rate * T.eff);
+  const double t_io = io_count(m, n, k, T.tm, T.tn, T.tk, 1, false) * word_bytes(dtype) /
+                      (f.hbm_gbps * 1e9);
+  return std::max(t_compute, t_io);
+}
+
 size_t workspace_bytes(const cosma_plan_info& p) {
   if (p.m <= 0 || p.n <= 0 || p.k <= 0) return 0;
   size_t ws = 0;

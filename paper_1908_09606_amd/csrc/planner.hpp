@@ -42,6 +42,10 @@ double io_count(int64_t m, int64_t n, int64_t k, int64_t tm, int64_t tn, int64_t
 double q_ea_bytes(int64_t m, int64_t n, int64_t k, int64_t k_split, int64_t splits, int tm,
                   int tn, int group_m, int64_t slots_per_xcd, int num_xcds, double w_bytes);
 
+// Modelled time of one problem inside a persistent batch with a given tile.
+double batch_item_cost(int64_t m, int64_t n, int64_t k, int dtype, int tile_id,
+                       const cosma_device_facts& f);
+
 // Device workspace a plan needs (split-K partials, Ozaki digit planes).
 size_t workspace_bytes(const cosma_plan_info& p);
 

@@ -46,7 +46,7 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("gemm_f64.hip", "tiles.hpp", "kernels.hpp"):
+    for name in ("gemm_f64.hip", "tiles.hpp", "kernels.hpp", "planner.cpp"):
         with open(os.path.join(ROOT, "paper_1908_09606_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -152,13 +152,17 @@ def main():
     # dominant kernel: the square product's GEMM launch (one kernel per call)
     dom = next((r for r in shape_rows if r["shape"] == "square"), shape_rows[0])
     dom_plan = next(p["plan"] for p in probs if p["name"] == dom["shape"])
-    kernel_tag = f"gemm_f64<{dom_plan.tile_m}x{dom_plan.tile_n}x{dom_plan.tile_k}>"
+    kernel_tag = (f"gemm_f64<{dom_plan.tile_m}x{dom_plan.tile_n}x{dom_plan.tile_k}> "
+                  f"group_m={dom_plan.group_m}")
     achieved = 2.0 * dom["m"] * dom["n"] * dom["k"] / (dom["ms_avg"] * 1e-3) / 1e12
+    traffic = committed_traffic(kernel_tag)
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_F64,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64, 4),
-                "traffic": committed_traffic(kernel_tag), "kernel": kernel_tag,
+                "traffic": traffic, "kernel": kernel_tag,
                 "launch": f"{dom['shape']} {dom['m']}x{dom['n']}x{dom['k']}",
-                "planner_q_ea_bytes": dom["planner_q_ea_bytes"]}
+                "planner_q_ea_bytes": dom["planner_q_ea_bytes"],
+                "traffic_over_q_ea": (round(traffic / dom["planner_q_ea_bytes"], 3)
+                                      if traffic else None)}
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1,

@@ -33,7 +33,7 @@ struct DeviceState {
 
 std::mutex g_mutex;
 DeviceState g_dev[kMaxDevices];
-std::map<std::tuple<int, int64_t, int64_t, int64_t, int>, cosma_plan_info> g_plans;
+std::map<std::tuple<int, int64_t, int64_t, int64_t, int, int>, cosma_plan_info> g_plans;
 
 double env_delta() {
   static double d = [] {
@@ -92,11 +92,13 @@ bool workspace_for_current(void** ptr, size_t* bytes) {
   return true;
 }
 
-int plan_cached(int64_t m, int64_t n, int64_t k, int dtype, cosma_plan_info* out) {
+int plan_cached(int64_t m, int64_t n, int64_t k, int dtype, cosma_plan_info* out,
+                int64_t a_pitch_bytes) {
   const int dev = current_device();
   int st = COSMA_OK;
   const cosma_device_facts f = device_facts(&st);
-  const auto key = std::make_tuple(dev, m, n, k, dtype);
+  if (a_pitch_bytes <= 0) a_pitch_bytes = k * (int64_t)word_bytes(dtype);
+  const auto key = std::make_tuple(dev, m, n, k, dtype, conflicting_pitch(a_pitch_bytes) ? 1 : 0);
   {
     std::lock_guard<std::mutex> lock(g_mutex);
     auto it = g_plans.find(key);
@@ -105,7 +107,7 @@ int plan_cached(int64_t m, int64_t n, int64_t k, int dtype, cosma_plan_info* out
       return COSMA_OK;
     }
   }
-  const int rc = make_plan(m, n, k, dtype, f, env_delta(), -1, -1, out);
+  const int rc = make_plan(m, n, k, dtype, f, env_delta(), -1, -1, out, a_pitch_bytes);
   if (rc != COSMA_OK) return rc;
   std::lock_guard<std::mutex> lock(g_mutex);
   if (g_plans.size() > 4096) g_plans.clear();
@@ -245,7 +247,7 @@ int cosma_gemm(int64_t m, int64_t n, int64_t k, double alpha, const void* A, int
   device_facts(&st);
   if (st != COSMA_OK) return st;
   cosma_plan_info plan;
-  rc = plan_cached(m, n, k, dtype, &plan);
+  rc = plan_cached(m, n, k, dtype, &plan, lda * (int64_t)word_bytes(dtype));
   if (rc != COSMA_OK) return rc;
   return run_plan(plan, alpha, A, lda, B, ldb, beta, C, ldc, (hipStream_t)stream);
 }

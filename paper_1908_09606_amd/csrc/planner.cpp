@@ -240,8 +240,12 @@ double launch_overhead_s() { return 4e-6; }
 
 }  // namespace
 
+bool conflicting_pitch(int64_t a_pitch_bytes) {
+  return a_pitch_bytes > 0 && a_pitch_bytes % 4096 == 0;
+}
+
 int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_facts& f,
-              double delta, int tile_id, int p_k, cosma_plan_info* out) {
+              double delta, int tile_id, int p_k, cosma_plan_info* out, int64_t a_pitch_bytes) {
   if (!out || m < 0 || n < 0 || k < 0) return COSMA_ERR_INVALID_ARG;
   int ntiles = 0;
   const TileDesc* menu = tile_menu(dtype, &ntiles);
@@ -299,6 +303,14 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
   const double mn = (double)m * (double)n;
   const int cus_per_xcd = std::max(1, f.num_cus / f.num_xcds);
 
+  // Rows of A whose pitch is a multiple of 4 KiB put the lines of one k
+  // offset into the same L2 sets; sharing an A panel across the tiles of an
+  // XCD then only works while the XCD's block holds few A rows (measured on
+  // the square FP64 product: 1.04x / 1.15x / 1.8x / 2.2x the sharing model
+  // with 256 / 512 / 1024 / 2048 rows).  Such pitches restrict the raster
+  // groups to at most 512 A rows.
+  if (a_pitch_bytes <= 0) a_pitch_bytes = k * (int64_t)word_bytes(dtype);
+  const bool pow2_pitch = dtype != F64_OZAKI_I8 && conflicting_pitch(a_pitch_bytes);
   static const int kSplits[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64};
   static const int kGroups[] = {1, 2, 4, 8, 16};
   std::vector<Candidate> cands;
@@ -322,6 +334,7 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
       int best_g = 1;
       for (int g : kGroups) {
         if (g > 1 && g > ceil_div(m, T.tm)) break;
+        if (g > 1 && pow2_pitch && g * T.tm > 512) break;
         const double q = q_ea_bytes(m, n, k, k_split, splits, T.tm, T.tn, g,
                                     (int64_t)cus_per_xcd * T.wg_per_cu, f.num_xcds, w);
         if (q < best_q * (1.0 - 1e-12)) {

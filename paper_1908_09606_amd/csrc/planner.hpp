@@ -52,7 +52,13 @@ size_t workspace_bytes(const cosma_plan_info& p);
 // ---- GPU plan -----------------------------------------------------------
 // Fill `out` for a given tile and split (tile_id < 0 / p_k <= 0: planner's
 // choice).  Returns a cosma_status.
+// a_pitch_bytes: A's row pitch (lda * element size); 0 means dense (k).
 int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_facts& f,
-              double delta, int tile_id, int p_k, cosma_plan_info* out);
+              double delta, int tile_id, int p_k, cosma_plan_info* out,
+              int64_t a_pitch_bytes = 0);
+
+// True when rows of A at the same k offset fall into the same L2 sets: a row
+// pitch that is a multiple of 4 KiB.
+bool conflicting_pitch(int64_t a_pitch_bytes);
 
 }  // namespace cosma

@@ -140,3 +140,14 @@ def test_gpu_entry_points_reject_bad_arguments_without_launching():
     assert cm.cosma_gemm(4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, 9, 0) == cm.COSMA_ERR_INVALID_ARG
     assert cm.cosma_gemm(4, 4, 4, 1.0, 12, 4, 8, 4, 0.0, 8, 4, 0, 0) == cm.COSMA_ERR_INVALID_ARG  # misaligned
     assert cm.cosma_gemm(0, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, 0, 0) == cm.COSMA_OK
+
+
+def test_raster_groups_respect_conflicting_pitch():
+    """A row pitch that is a multiple of 4 KiB puts the A-panel lines of one k
+    offset into the same L2 sets: the planner keeps at most 512 A rows per
+    raster group then; other pitches may use taller groups."""
+    for dtype in ("f64", "f32", "bf16x3"):
+        rc, p = cm.cosma_plan_query(16384, 16384, 16384, dtype)   # pitch 2^16 or 2^17 bytes
+        assert rc == 0 and (p.group_m == 1 or p.group_m * p.tile_m <= 512)
+    rc, p = cm.cosma_plan_query(16000, 16000, 16000, "f64")        # pitch 128000 bytes
+    assert rc == 0 and p.group_m * p.tile_m > 512

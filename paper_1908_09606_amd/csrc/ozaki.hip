@@ -8,16 +8,16 @@
 //   2. Digits: x = A[i][t] 2^-e_i lies in (-1, 1); with r_0 = x,
 //      d_u = trunc(2^7 r_(u-1)), r_u = 2^7 r_(u-1) - d_u (all exact in
 //      binary64), so x = sum_u d_u 2^-7u + r_s 2^-7s and |d_u| <= 127.
-//      Same for the columns of B.  Digit planes are int8, k padded to a
-//      multiple of 64 with zeros; A planes are [u][row][k], B planes are
-//      stored transposed, [u][col][k], so both MFMA operands are
-//      k-contiguous 16-byte runs.
+//      Same for the columns of B.  Digit planes are int8, stored in the
+//      GEMM's staging order (one contiguous block per slice, tile and k
+//      round; B transposed so that both MFMA operands are k-contiguous).
 //   3. Products: C[i][j] ~ 2^(e_i + f_j) sum_{u+v <= s+1} 2^-7(u+v) (A_u B_v)[i][j].
 //      Every A_u B_v is exact in int32 (v_mfma_i32_16x16x64_i8); the pairs of
 //      one anti-diagonal d = u + v share the scale 2^-7d, so they accumulate
-//      in one int32 register block.  Every 8192 k (|sum| < s 127^2 8192 <
-//      2^31) the s diagonal blocks are converted to binary64, scaled and
-//      added, smallest scale first, to the binary64 accumulators.
+//      in one int32 register block.  A work item covers at most 8192 k
+//      (|sum| <= s 127^2 8192 < 2^31); at its end the s diagonal blocks are
+//      converted to binary64, scaled and added, smallest scale first.
+//      Longer reductions are split and summed by the FP64 split-K reduction.
 //
 // The GEMM keeps its block of C resident and streams k in LDS-staged rounds
 // like the other kernels (Algorithm 1 / section 5); binary64 is used only for
@@ -40,8 +40,8 @@ namespace {
 typedef int i4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int KPAD = 64;          // digit planes: k padded to a multiple of 64
-constexpr int64_t FLUSH_K = 8192;  // int32 diagonal sums flushed every 8192 k
+constexpr int64_t MAX_K_ITEM = 8192;  // reduction length per work item (int32 exactness)
+constexpr int64_t COL_CHUNK = 256; // rows of B per block of the column-exponent pass
 
 // ---------------------------------------------------------------- exponents
 // One wave per row of A: e[i] = exponent of max_t |A[i][t]| (frexp form,
@@ -67,13 +67,13 @@ __global__ __launch_bounds__(256) void fill_int_kernel(int* __restrict__ p, int6
 }
 
 // Columns of B: thread per column (coalesced across the wave), blockIdx.y
-// per chunk of 1024 rows; partial maxima meet in an atomic max.
+// per chunk of COL_CHUNK rows; partial maxima meet in an atomic max.
 __global__ __launch_bounds__(256) void col_exp_kernel(const double* __restrict__ B, int64_t k,
                                                       int64_t n, int64_t ldb, int* __restrict__ f) {
   const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (col >= n) return;
-  const int64_t t0 = (int64_t)blockIdx.y * 1024;
-  const int64_t t1 = min64(k, t0 + 1024);
+  const int64_t t0 = (int64_t)blockIdx.y * COL_CHUNK;
+  const int64_t t1 = min64(k, t0 + COL_CHUNK);
   double mx = 0.0;
   for (int64_t t = t0; t < t1; ++t) mx = fmax(mx, fabs(B[t * ldb + col]));
   int ex = 0;
@@ -88,8 +88,14 @@ __global__ __launch_bounds__(256) void fix_exp_kernel(int* __restrict__ f, int64
 }
 
 // ---------------------------------------------------------------- digits
-// 16 consecutive values of one row (A) or one column (B) -> s planes of 16
-// int8 digits each.
+// Digit planes are stored in the order the GEMM consumes them: for slice u,
+// row tile T (OZ_BM rows of A, or OZ_BN columns of B) and k round R (OZ_BK
+// values), one contiguous block of rows x OZ_BK bytes, row-major:
+//   A: ((u * tiles_a + T) * rounds + R) * OZ_BM * OZ_BK + (row % OZ_BM) * OZ_BK + k % OZ_BK
+//   B: ((u * tiles_b + T) * rounds + R) * OZ_BN * OZ_BK + (col % OZ_BN) * OZ_BK + k % OZ_BK
+// Rows of padded tiles and k beyond the matrix hold zero digits.
+constexpr int OZ_BM = 128, OZ_BN = 64, OZ_BK = 64;
+
 __device__ __forceinline__ void digits16(double (&x)[16], int s, int8_t* __restrict__ out,
                                          int64_t plane_stride) {
   for (int u = 0; u < s; ++u) {
@@ -107,55 +113,90 @@ __device__ __forceinline__ void digits16(double (&x)[16], int s, int8_t* __restr
   }
 }
 
-// A: thread per (row, 16-wide k chunk); writes planes[u][row][kc..kc+15].
+// A: one workgroup per (row tile, k round): the 128 x 64 values are read in
+// 16-byte pieces, four rows of 256 contiguous bytes per wave instruction,
+// scaled and transposed through LDS; then each chunk c of 16 consecutive k
+// (row c / 4) is digitised and its 16 digit bytes per slice go to offset
+// 16 c of the tile's 8 KiB plane block.
 __global__ __launch_bounds__(256) void slice_a_kernel(const double* __restrict__ A, int64_t m,
                                                       int64_t k, int64_t lda,
                                                       const int* __restrict__ e, int s,
-                                                      int8_t* __restrict__ planes, int64_t kp) {
-  const int64_t chunks = kp / 16;
-  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (id >= m * chunks) return;
-  const int64_t row = id / chunks, kc = (id - row * chunks) * 16;
-  const int sh = -e[row];
-  double x[16];
+                                                      int8_t* __restrict__ planes, int64_t rows,
+                                                      int64_t kp) {
+  __shared__ double tile[OZ_BM][OZ_BK + 1];
+  const int64_t rounds = kp / OZ_BK;
+  const int64_t blk = blockIdx.x;  // row_tile * rounds + round
+  const int64_t r0 = (blk / rounds) * OZ_BM, k0 = (blk % rounds) * OZ_BK;
+  for (int c = threadIdx.x; c < OZ_BM * OZ_BK / 2; c += 256) {
+    const int r = c / (OZ_BK / 2), kk = (c % (OZ_BK / 2)) * 2;
+    const int64_t row = r0 + r;
+    double x0 = 0.0, x1 = 0.0;
+    if (row < m) {
+      const int sh = -e[row];
+      if (k0 + kk < k) x0 = ldexp(A[row * lda + k0 + kk], sh);
+      if (k0 + kk + 1 < k) x1 = ldexp(A[row * lda + k0 + kk + 1], sh);
+    }
+    tile[r][kk] = x0;
+    tile[r][kk + 1] = x1;
+  }
+  __syncthreads();
+  // 512 chunks of 16 values (128 rows x 4): two per thread
+  for (int h = 0; h < 2; ++h) {
+    const int c = threadIdx.x + 256 * h;
+    const int r = c >> 2, kk = (c & 3) * 16;
+    double x[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i)
-    x[i] = (kc + i < k) ? ldexp(A[row * lda + kc + i], sh) : 0.0;
-  digits16(x, s, planes + row * kp + kc, m * kp);
+    for (int i = 0; i < 16; ++i) x[i] = tile[r][kk + i];
+    digits16(x, s, planes + blk * (OZ_BM * OZ_BK) + c * 16, rows * kp);
+  }
 }
 
-// B: thread per (column, 16-wide k chunk), columns fastest across the wave;
-// writes the transposed planes[u][col][kc..kc+15].
+// B: thread per (column, 16-wide k chunk), columns fastest across the wave.
 __global__ __launch_bounds__(256) void slice_b_kernel(const double* __restrict__ B, int64_t k,
                                                       int64_t n, int64_t ldb,
                                                       const int* __restrict__ f, int s,
-                                                      int8_t* __restrict__ planes, int64_t kp) {
+                                                      int8_t* __restrict__ planes, int64_t cols,
+                                                      int64_t kp) {
   const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t chunks = kp / 16;
-  if (id >= n * chunks) return;
-  const int64_t kc = (id / n) * 16, col = id - (id / n) * n;
-  const int sh = -f[col];
+  if (id >= cols * chunks) return;
+  const int64_t kc = (id / cols) * 16, col = id - (id / cols) * cols;
   double x[16];
+  if (col < n) {
+    const int sh = -f[col];
 #pragma unroll
-  for (int i = 0; i < 16; ++i)
-    x[i] = (kc + i < k) ? ldexp(B[(kc + i) * ldb + col], sh) : 0.0;
-  digits16(x, s, planes + col * kp + kc, n * kp);
+    for (int i = 0; i < 16; ++i)
+      x[i] = (kc + i < k) ? ldexp(B[(kc + i) * ldb + col], sh) : 0.0;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = 0.0;
+  }
+  const int64_t rounds = kp / OZ_BK;
+  const int64_t off = ((col / OZ_BN) * rounds + kc / OZ_BK) * (OZ_BN * OZ_BK) +
+                      (col % OZ_BN) * OZ_BK + kc % OZ_BK;
+  digits16(x, s, planes + off, cols * kp);
 }
 
 // ---------------------------------------------------------------- GEMM
-// Work item: a 64 x 64 block of C, 4 waves of 32 x 32 (2 x 2 MFMA blocks).
-// LDS stage: s planes of A (64 rows) and of B (64 columns), 64 k each, rows
-// padded to 80 bytes.
-constexpr int OZ_BM = 64, OZ_BN = 64, OZ_BK = 64, OZ_ROW = 80;
+// Work item: a 128 x 64 block of C, 4 waves of 64 x 32 (4 x 2 blocks of
+// 16 x 16), v_mfma_i32_16x16x64_i8: lane l (r = l % 16, g = l / 16)
+// supplies A[r][16g .. 16g+15] and B[16g .. 16g+15][r] and holds
+// D[4g + v][r] in element v.  One round = 64 k.  The LDS stage holds the s
+// planes of A (128 rows) and of B (64 columns) with rows padded from 64 to
+// 80 bytes, so the 16-byte operand reads of 16 lanes hit 16 different bank
+// quads.  One stage (105 KiB for s = 7): the next round's planes are
+// prefetched into registers during the round and written after a barrier.
+constexpr int OZ_ROW = 80;
 
 struct OzArgs {
-  const int8_t* a_planes;  // [s][m][kp]
-  const int8_t* b_planes;  // [s][n][kp]
+  const int8_t* a_planes;
+  const int8_t* b_planes;
   const int* e;            // row exponents of A
   const int* f;            // column exponents of B
   double* C;
   double* P;
   int64_t m, n, k, kp, ldc;
+  int64_t a_rows, b_cols;  // padded rows of A / columns of B (plane extents)
   int64_t k_split, tiles_m, tiles_n, splits, ldp, split_stride;
   double alpha, beta;
   int group_m, num_xcds;
@@ -163,9 +204,9 @@ struct OzArgs {
 
 template <int S>
 __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
-  constexpr int PLANE = OZ_BM * OZ_ROW;   // bytes per plane in LDS (BM == BN)
-  constexpr int STAGE = 2 * S * PLANE;
-  __shared__ __attribute__((aligned(16))) int8_t lds[2][STAGE];
+  constexpr int A_PLANE = OZ_BM * OZ_ROW, B_PLANE = OZ_BN * OZ_ROW;
+  constexpr int STAGE = S * (A_PLANE + B_PLANE);
+  __shared__ __attribute__((aligned(16))) int8_t lds[STAGE];
 
   const int64_t l = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x, g.num_xcds);
   const ItemCoord ic = item_coord(l, g.tiles_m, g.tiles_n, g.group_m);
@@ -177,105 +218,97 @@ __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 15, lg = lane >> 4;
 
-  // staging map: thread -> (row/col r, 16-byte k chunk)
-  const int sr = t >> 2, sk = (t & 3) * 16;
-  const bool a_in = row0 + sr < g.m, b_in = col0 + sr < g.n;
-  const int8_t* a_src = g.a_planes + (row0 + sr) * g.kp + sk;
-  const int8_t* b_src = g.b_planes + (col0 + sr) * g.kp + sk;
-  const int64_t a_plane = g.m * g.kp, b_plane = g.n * g.kp;
+  // staging: plane blocks are contiguous (A 8 KiB, B 4 KiB per round);
+  // thread t moves A bytes [16t, 16t+16) and [4096 + 16t, ...), B bytes [16t, 16t+16)
+  const int64_t rounds = g.kp / OZ_BK;
+  const int64_t a_plane = g.a_rows * g.kp, b_plane = g.b_cols * g.kp;
+  const int8_t* a_src = g.a_planes + (ic.tile_row * rounds) * (OZ_BM * OZ_BK) + t * 16;
+  const int8_t* b_src = g.b_planes + (ic.tile_col * rounds) * (OZ_BN * OZ_BK) + t * 16;
+  const int a_dst0 = (t >> 2) * OZ_ROW + (t & 3) * 16;          // rows 0..63
+  const int a_dst1 = ((t >> 2) + 64) * OZ_ROW + (t & 3) * 16;   // rows 64..127
+  const int b_dst = (t >> 2) * OZ_ROW + (t & 3) * 16;
 
-  i4 acc[S][2][2];
-  d4 sum[2][2];
+  i4 acc[S][4][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int d = 0; d < S; ++d)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      sum[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int d = 0; d < S; ++d) acc[d][i][j] = i4{0, 0, 0, 0};
-    }
+      for (int j = 0; j < 2; ++j) acc[d][i][j] = i4{0, 0, 0, 0};
 
-  i4 ra[S], rb[S];
-  auto load = [&](int64_t k0) {
+  i4 ra0[S], ra1[S], rb[S];
+  auto load = [&](int64_t round) {
 #pragma unroll
     for (int u = 0; u < S; ++u) {
-      ra[u] = a_in ? *reinterpret_cast<const i4*>(a_src + u * a_plane + k0) : i4{0, 0, 0, 0};
-      rb[u] = b_in ? *reinterpret_cast<const i4*>(b_src + u * b_plane + k0) : i4{0, 0, 0, 0};
+      const int8_t* pa = a_src + u * a_plane + round * (OZ_BM * OZ_BK);
+      ra0[u] = *reinterpret_cast<const i4*>(pa);
+      ra1[u] = *reinterpret_cast<const i4*>(pa + 4096);
+      rb[u] = *reinterpret_cast<const i4*>(b_src + u * b_plane + round * (OZ_BN * OZ_BK));
     }
   };
-  auto store = [&](int8_t* st) {
+  auto store = [&]() {
 #pragma unroll
     for (int u = 0; u < S; ++u) {
-      *reinterpret_cast<i4*>(st + u * PLANE + sr * OZ_ROW + sk) = ra[u];
-      *reinterpret_cast<i4*>(st + (S + u) * PLANE + sr * OZ_ROW + sk) = rb[u];
+      *reinterpret_cast<i4*>(lds + u * A_PLANE + a_dst0) = ra0[u];
+      *reinterpret_cast<i4*>(lds + u * A_PLANE + a_dst1) = ra1[u];
+      *reinterpret_cast<i4*>(lds + S * A_PLANE + u * B_PLANE + b_dst) = rb[u];
     }
   };
-  auto flush = [&]() {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-#pragma unroll
-        for (int d = S - 1; d >= 0; --d) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            sum[i][j][v] += ldexp((double)acc[d][i][j][v], -7 * (d + 2));
-          acc[d][i][j] = i4{0, 0, 0, 0};
-        }
-      }
-  };
 
+  const int64_t rbeg = kbeg / OZ_BK;
   if (nk > 0) {
-    load(kbeg);
-    store(lds[0]);
+    load(rbeg);
+    store();
   }
   __syncthreads();
-  const int64_t rounds_per_flush = FLUSH_K / OZ_BK;
   for (int64_t kt = 0; kt < nk; ++kt) {
-    const int cur = (int)(kt & 1);
     const bool more = kt + 1 < nk;
-    if (more) load(kbeg + (kt + 1) * OZ_BK);
-    const int8_t* st = lds[cur];
+    if (more) load(rbeg + kt + 1);
     i4 bfr[S][2];
 #pragma unroll
     for (int v = 0; v < S; ++v)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        bfr[v][j] = *reinterpret_cast<const i4*>(st + (S + v) * PLANE +
+        bfr[v][j] = *reinterpret_cast<const i4*>(lds + S * A_PLANE + v * B_PLANE +
                                                  (wn * 32 + j * 16 + lr) * OZ_ROW + lg * 16);
 #pragma unroll
     for (int u = 0; u < S; ++u) {
-      i4 afr[2];
+      i4 afr[4];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        afr[i] = *reinterpret_cast<const i4*>(st + u * PLANE + (wm * 32 + i * 16 + lr) * OZ_ROW +
-                                              lg * 16);
+      for (int i = 0; i < 4; ++i)
+        afr[i] = *reinterpret_cast<const i4*>(lds + u * A_PLANE +
+                                              (wm * 64 + i * 16 + lr) * OZ_ROW + lg * 16);
 #pragma unroll
       for (int v = 0; v + u < S; ++v)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 2; ++j)
             acc[u + v][i][j] =
                 __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[i], bfr[v][j], acc[u + v][i][j], 0, 0, 0);
     }
-    if (more) store(lds[cur ^ 1]);
-    if ((kt + 1) % rounds_per_flush == 0) flush();
+    if (more) {
+      __syncthreads();  // every wave has finished reading this round's stage
+      store();
+    }
     __syncthreads();
   }
-  flush();
 
-  // epilogue: scale by 2^(e_i + f_j); standard 16x16 output layout
+  // epilogue: diagonal sums to binary64 (smallest scale first), scale by
+  // 2^(e_i + f_j); 16 x 16 output layout
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int64_t col = col0 + wn * 32 + j * 16 + lr;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = row0 + wm * 32 + i * 16 + lg * 4 + v;
+        const int64_t row = row0 + wm * 64 + i * 16 + lg * 4 + v;
         if (row < g.m && col < g.n) {
-          const double r = ldexp(sum[i][j][v], g.e[row] + g.f[col]);
+          double x = 0.0;
+#pragma unroll
+          for (int d = S - 1; d >= 0; --d) x += ldexp((double)acc[d][i][j][v], -7 * (d + 2));
+          const double r = ldexp(x, g.e[row] + g.f[col]);
           if (g.splits == 1) {
             double* p = g.C + row * g.ldc + col;
             const double y = g.alpha * r;
@@ -309,17 +342,19 @@ int run_ozaki(const cosma_plan_info& plan, double alpha, const void* A, int64_t 
               hipStream_t stream) {
   const int64_t m = plan.m, n = plan.n, k = plan.k;
   const int s = plan.slices;
-  if (s < 1 || s > 8 || plan.tile_m != OZ_BM || plan.tile_n != OZ_BN || plan.tile_k != OZ_BK)
+  if (s < 1 || s > 8 || plan.tile_m != OZ_BM || plan.tile_n != OZ_BN || plan.tile_k != OZ_BK ||
+      plan.k_split > MAX_K_ITEM)
     return COSMA_ERR_INVALID_ARG;
   if (m > INT_MAX / 4 || n > INT_MAX / 4) return COSMA_ERR_UNSUPPORTED;
-  const int64_t kp = ceil_div(k, KPAD) * KPAD;
+  const int64_t kp = ceil_div(k, OZ_BK) * OZ_BK;
+  const int64_t a_rows = ceil_div(m, OZ_BM) * OZ_BM, b_cols = ceil_div(n, OZ_BN) * OZ_BN;
   // workspace layout (matches workspace_bytes): partials | A planes, B planes | e, f
   auto up = [](size_t x) { return (x + 255) / 256 * 256; };
   char* w = static_cast<char*>(workspace);
   const size_t part = plan.p_k > 1 ? up((size_t)plan.p_k * m * n * sizeof(double)) : 0;
   int8_t* a_planes = reinterpret_cast<int8_t*>(w + part);
-  int8_t* b_planes = a_planes + (size_t)s * m * kp;
-  int* e = reinterpret_cast<int*>(w + part + up((size_t)s * kp * (m + n)));
+  int8_t* b_planes = a_planes + (size_t)s * a_rows * kp;
+  int* e = reinterpret_cast<int*>(w + part + up((size_t)s * kp * (a_rows + b_cols)));
   int* f = e + m;
   hipError_t err;
 
@@ -327,13 +362,14 @@ int run_ozaki(const cosma_plan_info& plan, double alpha, const void* A, int64_t 
                      static_cast<const double*>(A), m, k, lda, e);
   hipLaunchKernelGGL(fill_int_kernel, dim3(blocks_for(n) > 4096 ? 4096 : blocks_for(n)), dim3(256),
                      0, stream, f, n, INT_MIN);
-  hipLaunchKernelGGL(col_exp_kernel, dim3(blocks_for(n), (unsigned)ceil_div(k, 1024)), dim3(256), 0,
-                     stream, static_cast<const double*>(B), k, n, ldb, f);
+  hipLaunchKernelGGL(col_exp_kernel, dim3(blocks_for(n), (unsigned)ceil_div(k, COL_CHUNK)),
+                     dim3(256), 0, stream, static_cast<const double*>(B), k, n, ldb, f);
   hipLaunchKernelGGL(fix_exp_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, f, n);
-  hipLaunchKernelGGL(slice_a_kernel, dim3(blocks_for(m * (kp / 16))), dim3(256), 0, stream,
-                     static_cast<const double*>(A), m, k, lda, e, s, a_planes, kp);
-  hipLaunchKernelGGL(slice_b_kernel, dim3(blocks_for(n * (kp / 16))), dim3(256), 0, stream,
-                     static_cast<const double*>(B), k, n, ldb, f, s, b_planes, kp);
+  hipLaunchKernelGGL(slice_a_kernel, dim3((unsigned)((a_rows / OZ_BM) * (kp / OZ_BK))), dim3(256), 0,
+                     stream,
+                     static_cast<const double*>(A), m, k, lda, e, s, a_planes, a_rows, kp);
+  hipLaunchKernelGGL(slice_b_kernel, dim3(blocks_for(b_cols * (kp / 16))), dim3(256), 0, stream,
+                     static_cast<const double*>(B), k, n, ldb, f, s, b_planes, b_cols, kp);
   if ((err = hipGetLastError()) != hipSuccess) return COSMA_ERR_HIP;
 
   OzArgs g;
@@ -348,6 +384,8 @@ int run_ozaki(const cosma_plan_info& plan, double alpha, const void* A, int64_t 
   g.k = k;
   g.kp = kp;
   g.ldc = ldc;
+  g.a_rows = a_rows;
+  g.b_cols = b_cols;
   g.k_split = plan.k_split;
   g.tiles_m = plan.p_m;
   g.tiles_n = plan.p_n;

@@ -216,10 +216,11 @@ size_t workspace_bytes(const cosma_plan_info& p) {
   if (p.p_k > 1) ws += (size_t)p.p_k * (size_t)p.m * (size_t)p.n * (size_t)partial_bytes(p.dtype);
   ws = (ws + 255) / 256 * 256;
   if (p.dtype == F64_OZAKI_I8) {
-    // digit planes of A (m x kp) and of B (stored n x kp), k padded to 64,
-    // then per-row / per-column exponents
+    // digit planes of A (rows padded to 128) and of B (columns padded to 64),
+    // k padded to 64, then per-row / per-column exponents
     const size_t kp = (size_t)ceil_div(p.k, 64) * 64;
-    ws += ((size_t)p.slices * kp * ((size_t)p.m + (size_t)p.n) + 255) / 256 * 256;
+    const size_t rows = (size_t)ceil_div(p.m, 128) * 128, cols = (size_t)ceil_div(p.n, 64) * 64;
+    ws += ((size_t)p.slices * kp * (rows + cols) + 255) / 256 * 256;
     ws += (((size_t)p.m + (size_t)p.n) * sizeof(int32_t) + 255) / 256 * 256;
   }
   return ws;
@@ -311,7 +312,8 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
   // groups to at most 512 A rows.
   if (a_pitch_bytes <= 0) a_pitch_bytes = k * (int64_t)word_bytes(dtype);
   const bool pow2_pitch = dtype != F64_OZAKI_I8 && conflicting_pitch(a_pitch_bytes);
-  static const int kSplits[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16, 20, 24, 32, 48, 64};
+  static const int kSplits[] = {1,  2,  3,  4,  5,  6,   8,   10,  12,  16,  20,
+                                24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
   static const int kGroups[] = {1, 2, 4, 8, 16};
   std::vector<Candidate> cands;
   for (int id = 0; id < ntiles; ++id) {
@@ -324,6 +326,8 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
       if (p_k <= 0 && req > 1 && (double)k / req < 256.0) continue;  // keep rounds long
       const int64_t k_split = ceil_div(panels, req) * T.tk;
       const int64_t splits = ceil_div(k, k_split);
+      // Ozaki: a work item's int32 diagonal sums stay exact for <= 8192 k
+      if (dtype == F64_OZAKI_I8 && k_split > 8192) continue;
       if (p_k <= 0 && splits != req) continue;  // duplicate of a smaller request
       const int64_t items = tiles * splits;
       const int64_t slots = (int64_t)f.num_cus * T.wg_per_cu;

@@ -41,7 +41,7 @@ constexpr TileDesc kTilesBf16x3[] = {
     {256, 128, 32, 512, 1, 0.55},
 };
 constexpr TileDesc kTilesOzaki[] = {
-    {64, 64, 64, 256, 1, 0.45},
+    {128, 64, 64, 256, 1, 0.60},
 };
 
 COSMA_HD inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -253,25 +253,33 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_f32_batched_kernel(BatchArgs
 }
 
 // ------------------------------------------------------------- BF16x3
-// LDS holds four planes per stage, all k-contiguous with rows of BK bf16
-// plus 8 of padding: A_hi, A_lo as [row][k] and B_hi, B_lo as [col][k], so
+// LDS holds four planes per stage, all k-contiguous: A_hi, A_lo as [row][k]
+// and B_hi, B_lo as [col][k], rows of 32 bf16 (64 bytes) whose four 16-byte
+// chunks are XOR-swizzled (chunk c of row r at c ^ ((r ^ (r >> 2)) & 3)), so
 // every MFMA operand (8 consecutive k of one row / column) is one 16-byte
-// read.  Each thread stages 8 consecutive k of one A row (two 16-byte loads)
-// and 8 consecutive k of one B column (eight 4-byte loads, coalesced across
-// the lanes of a wave, which cover consecutive columns).
+// read and both these reads and the staging writes hit distinct bank quads.
+// Each thread stages 8 consecutive k of one A row (two 16-byte loads) and 8
+// consecutive k of one B column (eight 4-byte loads, coalesced across the
+// lanes of a wave, which cover consecutive columns).
 template <int BM, int BN, int BK, int WM, int WN>
 struct X3Tile {
   static constexpr int NT = WM * WN * 64;
   static constexpr int WTM = BM / WM, WTN = BN / WN;
   static constexpr int MI = WTM / 16, NI = WTN / 16;
-  static constexpr int LD = BK + 8;                        // bf16 per LDS row
+  static constexpr int LD = BK;                            // bf16 per LDS row
   static constexpr int A_CHUNKS = BM * BK / 8 / NT;        // 8-element pieces per thread
   static constexpr int B_CHUNKS = BK * BN / 8 / NT;
   static constexpr int A_PLANE = BM * LD, B_PLANE = BN * LD;
   static constexpr int STAGE = 2 * A_PLANE + 2 * B_PLANE;  // bf16 elements
-  static_assert(BK % 32 == 0 && (BM * BK / 8) % NT == 0 && (BK * BN / 8) % NT == 0, "tiling");
+  static_assert(BK == 32, "the LDS swizzle assumes 64-byte rows");
+  static_assert((BM * BK / 8) % NT == 0 && (BK * BN / 8) % NT == 0, "tiling");
   static_assert(2 * STAGE * 2 <= 160 * 1024, "LDS budget");
 };
+
+// Offset (in bf16) of 16-byte chunk `chunk` of LDS row `row`.
+__device__ __forceinline__ int x3_off(int row, int chunk) {
+  return row * 32 + ((chunk ^ row ^ (row >> 2)) & 3) * 8;
+}
 
 // Round-to-nearest-even split of 8 floats into bf16 hi and lo pieces.
 __device__ __forceinline__ void split8(const float (&x)[8], us8& hi, us8& lo) {
@@ -341,8 +349,8 @@ __device__ __forceinline__ void x3_store(unsigned short* stage, const float (&ra
     const int r = c / (BK / 8), kk = (c % (BK / 8)) * 8;
     us8 hi, lo;
     split8(ra[i], hi, lo);
-    *reinterpret_cast<us8*>(a_hi + r * TL::LD + kk) = hi;
-    *reinterpret_cast<us8*>(a_lo + r * TL::LD + kk) = lo;
+    *reinterpret_cast<us8*>(a_hi + x3_off(r, kk / 8)) = hi;
+    *reinterpret_cast<us8*>(a_lo + x3_off(r, kk / 8)) = lo;
   }
 #pragma unroll
   for (int i = 0; i < TL::B_CHUNKS; ++i) {
@@ -350,8 +358,8 @@ __device__ __forceinline__ void x3_store(unsigned short* stage, const float (&ra
     const int col = c % BN, kk = (c / BN) * 8;
     us8 hi, lo;
     split8(rb[i], hi, lo);
-    *reinterpret_cast<us8*>(b_hi + col * TL::LD + kk) = hi;
-    *reinterpret_cast<us8*>(b_lo + col * TL::LD + kk) = lo;
+    *reinterpret_cast<us8*>(b_hi + x3_off(col, kk / 8)) = hi;
+    *reinterpret_cast<us8*>(b_lo + x3_off(col, kk / 8)) = lo;
   }
 }
 
@@ -401,18 +409,20 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_bf16x3_kernel(GemmArgs g) {
     const unsigned short* a_lo = st + TL::A_PLANE;
     const unsigned short* b_hi = st + 2 * TL::A_PLANE;
     const unsigned short* b_lo = st + 2 * TL::A_PLANE + TL::B_PLANE;
-#pragma unroll
-    for (int h = 0; h < BK / 32; ++h) {
+    {
+      // rows of the fragments start at multiples of 16: the swizzle of
+      // row base + lr equals that of lr
+      const int frag = x3_off(lr, lg);
       bf8 ah[TL::MI], al[TL::MI], bh[TL::NI], bl[TL::NI];
 #pragma unroll
       for (int i = 0; i < TL::MI; ++i) {
-        const int off = (wm * TL::WTM + i * 16 + lr) * TL::LD + h * 32 + lg * 8;
+        const int off = (wm * TL::WTM + i * 16) * TL::LD + frag;
         ah[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(a_hi + off));
         al[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(a_lo + off));
       }
 #pragma unroll
       for (int j = 0; j < TL::NI; ++j) {
-        const int off = (wn * TL::WTN + j * 16 + lr) * TL::LD + h * 32 + lg * 8;
+        const int off = (wn * TL::WTN + j * 16) * TL::LD + frag;
         bh[j] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(b_hi + off));
         bl[j] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(b_lo + off));
       }

@@ -182,11 +182,18 @@ __global__ __launch_bounds__(256) void slice_b_kernel(const double* __restrict__
 // 16 x 16), v_mfma_i32_16x16x64_i8: lane l (r = l % 16, g = l / 16)
 // supplies A[r][16g .. 16g+15] and B[16g .. 16g+15][r] and holds
 // D[4g + v][r] in element v.  One round = 64 k.  The LDS stage holds the s
-// planes of A (128 rows) and of B (64 columns) with rows padded from 64 to
-// 80 bytes, so the 16-byte operand reads of 16 lanes hit 16 different bank
-// quads.  One stage (105 KiB for s = 7): the next round's planes are
-// prefetched into registers during the round and written after a barrier.
-constexpr int OZ_ROW = 80;
+// planes of A (128 rows) and of B (64 columns) as 64-byte rows whose four
+// 16-byte chunks are XOR-swizzled: chunk c of row r sits at position
+// c ^ ((r ^ (r >> 2)) & 3).  Both the operand reads (16 rows, one chunk) and
+// the staging writes (4 chunks of consecutive rows) then touch distinct bank
+// quads, for 32 banks (8 lanes per cycle) as well as 64 (16 lanes).  One
+// stage (86 KiB for s = 7): the next round's planes are prefetched into
+// registers during the round and written after a barrier.
+constexpr int OZ_ROW = 64;
+
+__device__ __forceinline__ int oz_swz(int row, int chunk) {
+  return row * OZ_ROW + ((chunk ^ row ^ (row >> 2)) & 3) * 16;
+}
 
 struct OzArgs {
   const int8_t* a_planes;
@@ -224,9 +231,12 @@ __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
   const int64_t a_plane = g.a_rows * g.kp, b_plane = g.b_cols * g.kp;
   const int8_t* a_src = g.a_planes + (ic.tile_row * rounds) * (OZ_BM * OZ_BK) + t * 16;
   const int8_t* b_src = g.b_planes + (ic.tile_col * rounds) * (OZ_BN * OZ_BK) + t * 16;
-  const int a_dst0 = (t >> 2) * OZ_ROW + (t & 3) * 16;          // rows 0..63
-  const int a_dst1 = ((t >> 2) + 64) * OZ_ROW + (t & 3) * 16;   // rows 64..127
-  const int b_dst = (t >> 2) * OZ_ROW + (t & 3) * 16;
+  const int a_dst0 = oz_swz(t >> 2, t & 3);         // rows 0..63
+  const int a_dst1 = oz_swz((t >> 2) + 64, t & 3);  // rows 64..127
+  const int b_dst = oz_swz(t >> 2, t & 3);
+  // operand reads: row base (a multiple of 16) + lr, chunk lg; the swizzle
+  // only depends on the row modulo 16
+  const int frag_off = oz_swz(lr, lg);
 
   i4 acc[S][4][2];
 #pragma unroll
@@ -270,22 +280,29 @@ __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
 #pragma unroll
       for (int j = 0; j < 2; ++j)
         bfr[v][j] = *reinterpret_cast<const i4*>(lds + S * A_PLANE + v * B_PLANE +
-                                                 (wn * 32 + j * 16 + lr) * OZ_ROW + lg * 16);
+                                                 (wn * 32 + j * 16) * OZ_ROW + frag_off);
+    // A fragments of slice u + 1 are read while the products of slice u run
+    const int8_t* a_frag = lds + wm * 64 * OZ_ROW + frag_off;
+    i4 afr[2][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      afr[0][i] = *reinterpret_cast<const i4*>(a_frag + i * 16 * OZ_ROW);
 #pragma unroll
     for (int u = 0; u < S; ++u) {
-      i4 afr[4];
+      if (u + 1 < S) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        afr[i] = *reinterpret_cast<const i4*>(lds + u * A_PLANE +
-                                              (wm * 64 + i * 16 + lr) * OZ_ROW + lg * 16);
+        for (int i = 0; i < 4; ++i)
+          afr[(u + 1) & 1][i] =
+              *reinterpret_cast<const i4*>(a_frag + (u + 1) * A_PLANE + i * 16 * OZ_ROW);
+      }
 #pragma unroll
       for (int v = 0; v + u < S; ++v)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 2; ++j)
-            acc[u + v][i][j] =
-                __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[i], bfr[v][j], acc[u + v][i][j], 0, 0, 0);
+            acc[u + v][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[u & 1][i], bfr[v][j],
+                                                                     acc[u + v][i][j], 0, 0, 0);
     }
     if (more) {
       __syncthreads();  // every wave has finished reading this round's stage

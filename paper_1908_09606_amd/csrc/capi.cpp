@@ -144,6 +144,57 @@ int check_args(int64_t m, int64_t n, int64_t k, double alpha, const void* A, int
 
 }  // namespace
 
+namespace {
+
+// BF16x3: split pass into the workspace planes, GEMM, split-K reduction.
+int run_bf16x3(const cosma_plan_info& plan, double alpha, const void* A, int64_t lda,
+               const void* B, int64_t ldb, double beta, void* C, int64_t ldc, void* ws,
+               hipStream_t stream) {
+  const int64_t m = plan.m, n = plan.n, k = plan.k;
+  X3Args g;
+  std::memset(&g, 0, sizeof(g));
+  g.kp = ceil_div(k, 32) * 32;
+  g.rows_p = ceil_div(m, 256) * 256;
+  g.cols_p = ceil_div(n, 128) * 128;
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  char* w = static_cast<char*>(ws);
+  const size_t part = plan.p_k > 1 ? up((size_t)plan.p_k * m * n * sizeof(float)) : 0;
+  unsigned short* base = reinterpret_cast<unsigned short*>(w + part);
+  g.a_hi = base;
+  g.a_lo = base + (size_t)g.rows_p * g.kp;
+  g.b_hi = base + (size_t)2 * g.rows_p * g.kp;
+  g.b_lo = base + (size_t)2 * g.rows_p * g.kp + (size_t)g.cols_p * g.kp;
+  g.C = C;
+  g.P = w;
+  g.ldc = ldc;
+  g.m = m;
+  g.n = n;
+  g.k_split = plan.k_split;
+  g.tiles_m = plan.p_m;
+  g.tiles_n = plan.p_n;
+  g.splits = plan.p_k;
+  g.ldp = n;
+  g.split_stride = m * n;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.group_m = plan.group_m > 0 ? plan.group_m : 1;
+  int st = COSMA_OK;
+  g.num_xcds = device_facts(&st).num_xcds;
+  hipError_t e = launch_bf16x3_split(static_cast<const float*>(A), m, k, lda,
+                                     static_cast<const float*>(B), n, ldb, g, stream);
+  if (e != hipSuccess) return COSMA_ERR_HIP;
+  e = launch_gemm_bf16x3(plan.tile_id, g, stream);
+  if (e != hipSuccess) return COSMA_ERR_HIP;
+  if (plan.p_k > 1) {
+    e = launch_splitk_reduce_f32((const float*)w, m * n, n, plan.p_k, (float*)C, ldc, m, n,
+                                 (float)alpha, (float)beta, stream);
+    if (e != hipSuccess) return COSMA_ERR_HIP;
+  }
+  return COSMA_OK;
+}
+
+}  // namespace
+
 // Run one product under `plan` (validated by the caller).
 int run_plan(const cosma_plan_info& plan, double alpha, const void* A, int64_t lda, const void* B,
              int64_t ldb, double beta, void* C, int64_t ldc, hipStream_t stream) {
@@ -165,6 +216,7 @@ int run_plan(const cosma_plan_info& plan, double alpha, const void* A, int64_t l
       return COSMA_ERR_WORKSPACE;
   }
   if (dtype == F64_OZAKI_I8) return run_ozaki(plan, alpha, A, lda, B, ldb, beta, C, ldc, ws, stream);
+  if (dtype == F32_BF16X3) return run_bf16x3(plan, alpha, A, lda, B, ldb, beta, C, ldc, ws, stream);
 
   GemmArgs g;
   std::memset(&g, 0, sizeof(g));
@@ -198,7 +250,6 @@ int run_plan(const cosma_plan_info& plan, double alpha, const void* A, int64_t l
   switch (dtype) {
     case F64: e = launch_gemm_f64(plan.tile_id, g, stream); break;
     case F32: e = launch_gemm_f32(plan.tile_id, g, stream); break;
-    case F32_BF16X3: e = launch_gemm_bf16x3(plan.tile_id, g, stream); break;
     default: return COSMA_ERR_INVALID_ARG;
   }
   if (e != hipSuccess) return COSMA_ERR_HIP;

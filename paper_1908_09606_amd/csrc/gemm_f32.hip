@@ -11,9 +11,11 @@
 //
 // Both keep the work item's block of C resident in accumulators and stream
 // k in LDS-staged rounds (the loop of Algorithm 1, section 5's resident
-// block), double-buffered as in section 7.3.  The bf16 split is done while
-// staging: FP32 panels are read from memory once, split in registers and
-// written to LDS as hi / lo planes, so no extra pass over A or B is needed.
+// block), double-buffered as in section 7.3.  For BF16x3 a split pass
+// first writes A and B once as bf16 hi / lo planes in the order the GEMM
+// stages them (32-wide k blocks of padded rows, zero padding), so the GEMM
+// moves contiguous 16-byte chunks straight into the swizzled LDS layout
+// with no conversion arithmetic and no bounds checks in its main loop.
 //
 // Matrix-core layouts (lane l, r = l % 16, g = l / 16):
 //   f32 16x16x4:  a = A[r][g], b = B[g][r], acc[v] = D[4g + v][r]
@@ -293,91 +295,81 @@ __device__ __forceinline__ void split8(const float (&x)[8], us8& hi, us8& lo) {
   }
 }
 
-template <class TL, int BM, int BN, int BK, bool CHECK>
-__device__ __forceinline__ void x3_load(const GemmArgs& g, int64_t row0, int64_t col0, int64_t k0,
-                                        int64_t kend, float (&ra)[TL::A_CHUNKS][8],
-                                        float (&rb)[TL::B_CHUNKS][8]) {
-  const float* __restrict__ A = static_cast<const float*>(g.A);
-  const float* __restrict__ B = static_cast<const float*>(g.B);
-  const int t = threadIdx.x;
+// Split pass: FP32 operands -> bf16 hi / lo planes in the GEMM's staging
+// order.  A plane: element (row, k) at ((k / 32) * rows_p + row) * 32 + k % 32
+// (rows_p = rows padded to X3_ROWS); B planes are stored transposed,
+// (col, k) at ((k / 32) * cols_p + col) * 32 + k % 32.  Padding rows,
+// columns and k hold zeros, so a tile's round of any tile shape is one
+// contiguous block and the GEMM needs no bounds checks on its loads.
+constexpr int X3_ROWS = 256, X3_COLS = 128, X3_K = 32;
+
+// A: thread per (row, 8 consecutive k); four threads cover one row's round.
+__global__ __launch_bounds__(256) void x3_split_a_kernel(const float* __restrict__ A, int64_t m,
+                                                         int64_t k, int64_t lda, int64_t rows_p,
+                                                         int64_t kp, unsigned short* __restrict__ hi,
+                                                         unsigned short* __restrict__ lo) {
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t per_round = rows_p * 4;
+  if (id >= per_round * (kp / X3_K)) return;
+  const int64_t round = id / per_round, rem = id - round * per_round;
+  const int64_t row = rem / 4, kc = round * X3_K + (rem % 4) * 8;
+  float x[8];
 #pragma unroll
-  for (int i = 0; i < TL::A_CHUNKS; ++i) {
-    const int c = t + TL::NT * i;
-    const int r = c / (BK / 8), kk = (c % (BK / 8)) * 8;
-    const int64_t gr = row0 + r, gk = k0 + kk;
-    if (!CHECK) {
-      const f4 a0 = *reinterpret_cast<const f4*>(A + gr * g.lda + gk);
-      const f4 a1 = *reinterpret_cast<const f4*>(A + gr * g.lda + gk + 4);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        ra[i][e] = a0[e];
-        ra[i][4 + e] = a1[e];
-      }
-    } else {
-      const bool rin = gr < g.m;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) ra[i][e] = (rin && gk + e < kend) ? A[gr * g.lda + gk + e] : 0.0f;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < TL::B_CHUNKS; ++i) {
-    const int c = t + TL::NT * i;
-    const int col = c % BN, kk = (c / BN) * 8;
-    const int64_t gc = col0 + col, gk = k0 + kk;
-    if (!CHECK) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) rb[i][e] = B[(gk + e) * g.ldb + gc];
-    } else {
-      const bool cin = gc < g.n;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) rb[i][e] = (cin && gk + e < kend) ? B[(gk + e) * g.ldb + gc] : 0.0f;
-    }
-  }
+  for (int e = 0; e < 8; ++e)
+    x[e] = (row < m && kc + e < k) ? A[row * lda + kc + e] : 0.0f;
+  us8 h, l;
+  split8(x, h, l);
+  const int64_t off = (round * rows_p + row) * X3_K + (rem % 4) * 8;
+  *reinterpret_cast<us8*>(hi + off) = h;
+  *reinterpret_cast<us8*>(lo + off) = l;
 }
 
-template <class TL, int BM, int BN, int BK>
-__device__ __forceinline__ void x3_store(unsigned short* stage, const float (&ra)[TL::A_CHUNKS][8],
-                                         const float (&rb)[TL::B_CHUNKS][8]) {
-  unsigned short* a_hi = stage;
-  unsigned short* a_lo = stage + TL::A_PLANE;
-  unsigned short* b_hi = stage + 2 * TL::A_PLANE;
-  unsigned short* b_lo = stage + 2 * TL::A_PLANE + TL::B_PLANE;
-  const int t = threadIdx.x;
+// B: thread per (column, 8 consecutive k), columns fastest across the wave.
+__global__ __launch_bounds__(256) void x3_split_b_kernel(const float* __restrict__ B, int64_t k,
+                                                         int64_t n, int64_t ldb, int64_t cols_p,
+                                                         int64_t kp, unsigned short* __restrict__ hi,
+                                                         unsigned short* __restrict__ lo) {
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (id >= cols_p * (kp / 8)) return;
+  const int64_t kc = (id / cols_p) * 8, col = id % cols_p;
+  float x[8];
 #pragma unroll
-  for (int i = 0; i < TL::A_CHUNKS; ++i) {
-    const int c = t + TL::NT * i;
-    const int r = c / (BK / 8), kk = (c % (BK / 8)) * 8;
-    us8 hi, lo;
-    split8(ra[i], hi, lo);
-    *reinterpret_cast<us8*>(a_hi + x3_off(r, kk / 8)) = hi;
-    *reinterpret_cast<us8*>(a_lo + x3_off(r, kk / 8)) = lo;
-  }
-#pragma unroll
-  for (int i = 0; i < TL::B_CHUNKS; ++i) {
-    const int c = t + TL::NT * i;
-    const int col = c % BN, kk = (c / BN) * 8;
-    us8 hi, lo;
-    split8(rb[i], hi, lo);
-    *reinterpret_cast<us8*>(b_hi + x3_off(col, kk / 8)) = hi;
-    *reinterpret_cast<us8*>(b_lo + x3_off(col, kk / 8)) = lo;
-  }
+  for (int e = 0; e < 8; ++e)
+    x[e] = (col < n && kc + e < k) ? B[(kc + e) * ldb + col] : 0.0f;
+  us8 h, l;
+  split8(x, h, l);
+  const int64_t off = ((kc / X3_K) * cols_p + col) * X3_K + kc % X3_K;
+  *reinterpret_cast<us8*>(hi + off) = h;
+  *reinterpret_cast<us8*>(lo + off) = l;
 }
+
+// GEMM on the split planes.  Staging per round: the tile's A_hi, A_lo
+// (BM rows x 64 bytes each) and B_hi, B_lo (BN columns x 64 bytes) blocks
+// are contiguous; thread t copies 16-byte chunks c = t + NT*i, chunk c of a
+// block being row c / 4, k chunk c % 4, into the swizzled LDS rows.
+template <class TL, int BM, int BN>
+struct X3Stage {
+  static constexpr int A_LD = BM * 4 / TL::NT;  // 16-byte chunks per thread per A plane
+  static constexpr int B_LD = BN * 4 / TL::NT;
+  static_assert(BM * 4 % TL::NT == 0 && BN * 4 % TL::NT == 0, "staging map");
+};
 
 template <int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(WM* WN * 64) void gemm_bf16x3_kernel(GemmArgs g) {
+__global__ __launch_bounds__(WM* WN * 64) void gemm_bf16x3_kernel(X3Args g) {
   using TL = X3Tile<BM, BN, BK, WM, WN>;
+  using SM = X3Stage<TL, BM, BN>;
   __shared__ __attribute__((aligned(16))) unsigned short lds[2][TL::STAGE];
 
   const int64_t l = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x, g.num_xcds);
   const ItemCoord ic = item_coord(l, g.tiles_m, g.tiles_n, g.group_m);
   const int64_t row0 = ic.tile_row * BM, col0 = ic.tile_col * BN;
   const int64_t kbeg = ic.split * g.k_split;
-  const int64_t kend = min64(g.k, kbeg + g.k_split);
+  const int64_t kend = min64(g.kp, kbeg + g.k_split);
   const int64_t nk = ceil_div(kend - kbeg, BK);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int lr = lane & 15, lg = lane >> 4;
-  const bool full_mn = (row0 + BM <= g.m) && (col0 + BN <= g.n) && g.vec_a;
 
   f4 acc[TL::MI][TL::NI];
 #pragma unroll
@@ -385,61 +377,113 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_bf16x3_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < TL::NI; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  float ra[TL::A_CHUNKS][8], rb[TL::B_CHUNKS][8];
-  if (nk > 0) {
-    if (full_mn && kbeg + BK <= kend)
-      x3_load<TL, BM, BN, BK, false>(g, row0, col0, kbeg, kend, ra, rb);
-    else
-      x3_load<TL, BM, BN, BK, true>(g, row0, col0, kbeg, kend, ra, rb);
-    x3_store<TL, BM, BN, BK>(lds[0], ra, rb);
-  }
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const int cur = (int)(kt & 1);
-    const bool more = kt + 1 < nk;
-    if (more) {
-      const int64_t k0 = kbeg + (kt + 1) * BK;
-      if (full_mn && k0 + BK <= kend)
-        x3_load<TL, BM, BN, BK, false>(g, row0, col0, k0, kend, ra, rb);
-      else
-        x3_load<TL, BM, BN, BK, true>(g, row0, col0, k0, kend, ra, rb);
+  // per-thread sources (bf16 units) of round 0 of this item, and LDS targets
+  const int64_t a_step = g.rows_p * X3_K, b_step = g.cols_p * X3_K;  // one round further
+  const unsigned short* a_hi_src = g.a_hi + (kbeg / X3_K) * a_step + row0 * X3_K;
+  const unsigned short* a_lo_src = g.a_lo + (kbeg / X3_K) * a_step + row0 * X3_K;
+  const unsigned short* b_hi_src = g.b_hi + (kbeg / X3_K) * b_step + col0 * X3_K;
+  const unsigned short* b_lo_src = g.b_lo + (kbeg / X3_K) * b_step + col0 * X3_K;
+  // two register sets: the loads of round r + 2 are issued at the start of
+  // round r and reach LDS at the end of round r + 1 (two rounds of latency
+  // hiding), while LDS holds rounds r and r + 1
+  us8 ra_h[2][SM::A_LD], ra_l[2][SM::A_LD], rb_h[2][SM::B_LD], rb_l[2][SM::B_LD];
+  auto load = [&](int set, int64_t round) {
+#pragma unroll
+    for (int i = 0; i < SM::A_LD; ++i) {
+      const int64_t o = round * a_step + (t + TL::NT * i) * 8;
+      ra_h[set][i] = *reinterpret_cast<const us8*>(a_hi_src + o);
+      ra_l[set][i] = *reinterpret_cast<const us8*>(a_lo_src + o);
     }
-    const unsigned short* st = lds[cur];
+#pragma unroll
+    for (int i = 0; i < SM::B_LD; ++i) {
+      const int64_t o = round * b_step + (t + TL::NT * i) * 8;
+      rb_h[set][i] = *reinterpret_cast<const us8*>(b_hi_src + o);
+      rb_l[set][i] = *reinterpret_cast<const us8*>(b_lo_src + o);
+    }
+  };
+  auto store = [&](int set, unsigned short* st) {
+    unsigned short* a_hi = st;
+    unsigned short* a_lo = st + TL::A_PLANE;
+    unsigned short* b_hi = st + 2 * TL::A_PLANE;
+    unsigned short* b_lo = st + 2 * TL::A_PLANE + TL::B_PLANE;
+#pragma unroll
+    for (int i = 0; i < SM::A_LD; ++i) {
+      const int c = t + TL::NT * i;
+      const int o = x3_off(c >> 2, c & 3);
+      *reinterpret_cast<us8*>(a_hi + o) = ra_h[set][i];
+      *reinterpret_cast<us8*>(a_lo + o) = ra_l[set][i];
+    }
+#pragma unroll
+    for (int i = 0; i < SM::B_LD; ++i) {
+      const int c = t + TL::NT * i;
+      const int o = x3_off(c >> 2, c & 3);
+      *reinterpret_cast<us8*>(b_hi + o) = rb_h[set][i];
+      *reinterpret_cast<us8*>(b_lo + o) = rb_l[set][i];
+    }
+  };
+  const int frag = x3_off(lr, lg);
+  auto compute = [&](const unsigned short* st) {
     const unsigned short* a_hi = st;
     const unsigned short* a_lo = st + TL::A_PLANE;
     const unsigned short* b_hi = st + 2 * TL::A_PLANE;
     const unsigned short* b_lo = st + 2 * TL::A_PLANE + TL::B_PLANE;
-    {
-      // rows of the fragments start at multiples of 16: the swizzle of
-      // row base + lr equals that of lr
-      const int frag = x3_off(lr, lg);
-      bf8 ah[TL::MI], al[TL::MI], bh[TL::NI], bl[TL::NI];
+    bf8 ah[TL::MI], al[TL::MI], bh[TL::NI], bl[TL::NI];
 #pragma unroll
-      for (int i = 0; i < TL::MI; ++i) {
-        const int off = (wm * TL::WTM + i * 16) * TL::LD + frag;
-        ah[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(a_hi + off));
-        al[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(a_lo + off));
-      }
+    for (int i = 0; i < TL::MI; ++i) {
+      const int off = (wm * TL::WTM + i * 16) * TL::LD + frag;
+      ah[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(a_hi + off));
+      al[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(a_lo + off));
+    }
+#pragma unroll
+    for (int j = 0; j < TL::NI; ++j) {
+      const int off = (wn * TL::WTN + j * 16) * TL::LD + frag;
+      bh[j] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(b_hi + off));
+      bl[j] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(b_lo + off));
+    }
+    // small terms first
+#pragma unroll
+    for (int i = 0; i < TL::MI; ++i)
 #pragma unroll
       for (int j = 0; j < TL::NI; ++j) {
-        const int off = (wn * TL::WTN + j * 16) * TL::LD + frag;
-        bh[j] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(b_hi + off));
-        bl[j] = __builtin_bit_cast(bf8, *reinterpret_cast<const us8*>(b_lo + off));
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
       }
-      // small terms first
-#pragma unroll
-      for (int i = 0; i < TL::MI; ++i)
-#pragma unroll
-        for (int j = 0; j < TL::NI; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-        }
-    }
-    if (more) x3_store<TL, BM, BN, BK>(lds[cur ^ 1], ra, rb);
+  };
+  // one round: prefetch round kt + 2 into `set`, compute round kt from LDS
+  // stage kt % 2 (== set), store round kt + 1 (register set 1 - set) into
+  // the other stage
+  auto round_step = [&](int set, int64_t kt) {
+    if (kt + 2 < nk) load(set, kt + 2);
+    compute(lds[set]);
+    if (kt + 1 < nk) store(1 - set, lds[1 - set]);
     __syncthreads();
+  };
+
+  if (nk > 0) {
+    load(0, 0);
+    if (nk > 1) load(1, 1);
+    store(0, lds[0]);
   }
-  f32_epilogue<TL::MI, TL::NI, TL::WTM, TL::WTN>(g, ic, row0, col0, wm, wn, lr, lg, acc);
+  __syncthreads();
+  int64_t kt = 0;
+  for (; kt + 1 < nk; kt += 2) {
+    round_step(0, kt);
+    round_step(1, kt + 1);
+  }
+  if (kt < nk) round_step(0, kt);
+  GemmArgs e;
+  e.C = g.C;
+  e.P = g.P;
+  e.ldc = g.ldc;
+  e.m = g.m;
+  e.n = g.n;
+  e.splits = g.splits;
+  e.ldp = g.ldp;
+  e.split_stride = g.split_stride;
+  e.alpha = g.alpha;
+  e.beta = g.beta;
+  f32_epilogue<TL::MI, TL::NI, TL::WTM, TL::WTN>(e, ic, row0, col0, wm, wn, lr, lg, acc);
 }
 
 template <class K>
@@ -494,11 +538,32 @@ int batched_occupancy_f32(int tile_id) {
   }
 }
 
-hipError_t launch_gemm_bf16x3(int tile_id, const GemmArgs& g, hipStream_t s) {
+template <class K>
+hipError_t launch_x3(K kernel, int threads, const X3Args& g, hipStream_t s) {
+  const int64_t items = g.tiles_m * g.tiles_n * g.splits;
+  if (items <= 0) return hipSuccess;
+  if (items > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)items), dim3(threads), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_bf16x3_split(const float* A, int64_t m, int64_t k, int64_t lda, const float* B,
+                               int64_t n, int64_t ldb, const X3Args& g, hipStream_t s) {
+  const int64_t ta = g.rows_p * 4 * (g.kp / X3_K), tb = g.cols_p * (g.kp / 8);
+  hipLaunchKernelGGL(x3_split_a_kernel, dim3((unsigned)((ta + 255) / 256)), dim3(256), 0, s, A, m,
+                     k, lda, g.rows_p, g.kp, const_cast<unsigned short*>(g.a_hi),
+                     const_cast<unsigned short*>(g.a_lo));
+  hipLaunchKernelGGL(x3_split_b_kernel, dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, s, B, k,
+                     n, ldb, g.cols_p, g.kp, const_cast<unsigned short*>(g.b_hi),
+                     const_cast<unsigned short*>(g.b_lo));
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_bf16x3(int tile_id, const X3Args& g, hipStream_t s) {
   switch (tile_id) {
-    case 0: return launch_items(gemm_bf16x3_kernel<128, 128, 32, 2, 2>, 256, g, s);
-    case 1: return launch_items(gemm_bf16x3_kernel<64, 64, 32, 2, 2>, 256, g, s);
-    case 2: return launch_items(gemm_bf16x3_kernel<256, 128, 32, 4, 2>, 512, g, s);
+    case 0: return launch_x3(gemm_bf16x3_kernel<128, 128, 32, 2, 2>, 256, g, s);
+    case 1: return launch_x3(gemm_bf16x3_kernel<64, 64, 32, 2, 2>, 256, g, s);
+    case 2: return launch_x3(gemm_bf16x3_kernel<256, 128, 32, 4, 2>, 512, g, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -55,8 +55,31 @@ struct BatchArgs {
 hipError_t launch_gemm_f64(int tile_id, const GemmArgs& g, hipStream_t s);
 // FP32 MFMA GEMM (tile menu kTilesF32).
 hipError_t launch_gemm_f32(int tile_id, const GemmArgs& g, hipStream_t s);
-// FP32-accurate GEMM from three bf16 products (tile menu kTilesBf16x3).
-hipError_t launch_gemm_bf16x3(int tile_id, const GemmArgs& g, hipStream_t s);
+// BF16x3: operands pre-split into bf16 hi / lo planes in staging order
+// (element (row, k) of A at ((k / 32) * rows_p + row) * 32 + k % 32; B
+// transposed likewise with cols_p); rows_p, cols_p multiples of 256 / 128,
+// kp of 32, padding zero.
+struct X3Args {
+  const unsigned short* a_hi;
+  const unsigned short* a_lo;
+  const unsigned short* b_hi;
+  const unsigned short* b_lo;
+  void* C;
+  void* P;
+  int64_t ldc;
+  int64_t m, n, kp;          // kp: padded k
+  int64_t rows_p, cols_p;    // padded plane extents
+  int64_t k_split;           // multiple of 32
+  int64_t tiles_m, tiles_n, splits;
+  int64_t ldp, split_stride;
+  double alpha, beta;
+  int group_m, num_xcds;
+};
+// Split pass (writes the four planes) and the GEMM on them (tile menu
+// kTilesBf16x3).
+hipError_t launch_bf16x3_split(const float* A, int64_t m, int64_t k, int64_t lda, const float* B,
+                               int64_t n, int64_t ldb, const X3Args& g, hipStream_t s);
+hipError_t launch_gemm_bf16x3(int tile_id, const X3Args& g, hipStream_t s);
 
 // Persistent batched launches (grid = resident workgroups) for a tile variant.
 hipError_t launch_batched_f64(int tile_id, const BatchArgs& b, int grid, hipStream_t s);

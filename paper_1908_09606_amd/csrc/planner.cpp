@@ -215,6 +215,13 @@ size_t workspace_bytes(const cosma_plan_info& p) {
   size_t ws = 0;
   if (p.p_k > 1) ws += (size_t)p.p_k * (size_t)p.m * (size_t)p.n * (size_t)partial_bytes(p.dtype);
   ws = (ws + 255) / 256 * 256;
+  if (p.dtype == F32_BF16X3) {
+    // bf16 hi and lo planes of A (rows padded to 256) and B (columns padded
+    // to 128, transposed), k padded to 32
+    const size_t kp = (size_t)ceil_div(p.k, 32) * 32;
+    const size_t rows = (size_t)ceil_div(p.m, 256) * 256, cols = (size_t)ceil_div(p.n, 128) * 128;
+    ws += (2 * 2 * kp * (rows + cols) + 255) / 256 * 256;
+  }
   if (p.dtype == F64_OZAKI_I8) {
     // digit planes of A (rows padded to 128) and of B (columns padded to 64),
     // k padded to 64, then per-row / per-column exponents

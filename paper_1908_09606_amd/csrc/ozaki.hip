@@ -88,11 +88,15 @@ __global__ __launch_bounds__(256) void fix_exp_kernel(int* __restrict__ f, int64
 }
 
 // ---------------------------------------------------------------- digits
-// Digit planes are stored in the order the GEMM consumes them: for slice u,
+// Digit planes are stored in the order the GEMM consumes them.  For slice u,
 // row tile T (OZ_BM rows of A, or OZ_BN columns of B) and k round R (OZ_BK
-// values), one contiguous block of rows x OZ_BK bytes, row-major:
-//   A: ((u * tiles_a + T) * rounds + R) * OZ_BM * OZ_BK + (row % OZ_BM) * OZ_BK + k % OZ_BK
-//   B: ((u * tiles_b + T) * rounds + R) * OZ_BN * OZ_BK + (col % OZ_BN) * OZ_BK + k % OZ_BK
+// values) there is one contiguous block, made of 1 KiB operand fragments of
+// v_mfma_i32_16x16x64_i8: fragment f covers 16 rows (columns of B) and the
+// round's 64 k, and lane l = 16 g + r of the instruction takes bytes
+// [16 l, 16 l + 16) = digits of row 16 f + r, k = 64 R + 16 g .. + 15:
+//   A: ((u * tiles_a + T) * rounds + R) * OZ_BM * OZ_BK
+//        + ((row % OZ_BM) / 16) * 1024 + (16 g + row % 16) * 16 + k % 16
+//   B: likewise with col for row, OZ_BN for OZ_BM
 // Rows of padded tiles and k beyond the matrix hold zero digits.
 constexpr int OZ_BM = 128, OZ_BN = 64, OZ_BK = 64;
 
@@ -113,11 +117,16 @@ __device__ __forceinline__ void digits16(double (&x)[16], int s, int8_t* __restr
   }
 }
 
+// Byte offset, inside a tile's block, of the 16 digits of row (or column)
+// rr of the tile and k chunk g (k % 64 in [16 g, 16 g + 16)).
+__device__ __forceinline__ int frag_offset(int rr, int g) {
+  return (rr >> 4) * 1024 + (g * 16 + (rr & 15)) * 16;
+}
+
 // A: one workgroup per (row tile, k round): the 128 x 64 values are read in
 // 16-byte pieces, four rows of 256 contiguous bytes per wave instruction,
-// scaled and transposed through LDS; then each chunk c of 16 consecutive k
-// (row c / 4) is digitised and its 16 digit bytes per slice go to offset
-// 16 c of the tile's 8 KiB plane block.
+// scaled and transposed through LDS; then each chunk of 16 consecutive k is
+// digitised and its 16 digit bytes per slice go to their fragment slot.
 __global__ __launch_bounds__(256) void slice_a_kernel(const double* __restrict__ A, int64_t m,
                                                       int64_t k, int64_t lda,
                                                       const int* __restrict__ e, int s,
@@ -147,7 +156,7 @@ __global__ __launch_bounds__(256) void slice_a_kernel(const double* __restrict__
     double x[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) x[i] = tile[r][kk + i];
-    digits16(x, s, planes + blk * (OZ_BM * OZ_BK) + c * 16, rows * kp);
+    digits16(x, s, planes + blk * (OZ_BM * OZ_BK) + frag_offset(r, c & 3), rows * kp);
   }
 }
 
@@ -173,7 +182,7 @@ __global__ __launch_bounds__(256) void slice_b_kernel(const double* __restrict__
   }
   const int64_t rounds = kp / OZ_BK;
   const int64_t off = ((col / OZ_BN) * rounds + kc / OZ_BK) * (OZ_BN * OZ_BK) +
-                      (col % OZ_BN) * OZ_BK + kc % OZ_BK;
+                      frag_offset((int)(col % OZ_BN), (int)((kc % OZ_BK) / 16));
   digits16(x, s, planes + off, cols * kp);
 }
 
@@ -181,19 +190,15 @@ __global__ __launch_bounds__(256) void slice_b_kernel(const double* __restrict__
 // Work item: a 128 x 64 block of C, 4 waves of 64 x 32 (4 x 2 blocks of
 // 16 x 16), v_mfma_i32_16x16x64_i8: lane l (r = l % 16, g = l / 16)
 // supplies A[r][16g .. 16g+15] and B[16g .. 16g+15][r] and holds
-// D[4g + v][r] in element v.  One round = 64 k.  The LDS stage holds the s
-// planes of A (128 rows) and of B (64 columns) as 64-byte rows whose four
-// 16-byte chunks are XOR-swizzled: chunk c of row r sits at position
-// c ^ ((r ^ (r >> 2)) & 3).  Both the operand reads (16 rows, one chunk) and
-// the staging writes (4 chunks of consecutive rows) then touch distinct bank
-// quads, for 32 banks (8 lanes per cycle) as well as 64 (16 lanes).  One
-// stage (86 KiB for s = 7): the next round's planes are prefetched into
-// registers during the round and written after a barrier.
-constexpr int OZ_ROW = 64;
-
-__device__ __forceinline__ int oz_swz(int row, int chunk) {
-  return row * OZ_ROW + ((chunk ^ row ^ (row >> 2)) & 3) * 16;
-}
+// D[4g + v][r] in element v.  One round = 64 k.
+//
+// The s planes of A (8 KiB each per round) go through two LDS stages, moved
+// by 16-byte global-to-LDS DMA (no registers, no conversion: the planes are
+// already fragments, and each wave instruction moves one 1 KiB fragment);
+// the next round's stage fills while the MFMAs run on the current one.  The
+// two B fragments of each plane that a wave needs are loaded straight into
+// registers one round ahead.  LDS per block: 2 s 8 KiB (112 KiB at s = 7).
+typedef __attribute__((address_space(3))) void* lds_ptr;
 
 struct OzArgs {
   const int8_t* a_planes;
@@ -211,9 +216,11 @@ struct OzArgs {
 
 template <int S>
 __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
-  constexpr int A_PLANE = OZ_BM * OZ_ROW, B_PLANE = OZ_BN * OZ_ROW;
-  constexpr int STAGE = S * (A_PLANE + B_PLANE);
-  __shared__ __attribute__((aligned(16))) int8_t lds[STAGE];
+  constexpr int A_BLK = OZ_BM * OZ_BK, B_BLK = OZ_BN * OZ_BK;
+  constexpr int STAGE = S * A_BLK;
+  constexpr int A_FRAGS = S * (A_BLK / 1024);  // 1 KiB fragments per stage
+  static_assert(A_FRAGS % 4 == 0, "fragments per wave");
+  __shared__ __attribute__((aligned(1024))) int8_t lds[2 * STAGE];
 
   const int64_t l = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x, g.num_xcds);
   const ItemCoord ic = item_coord(l, g.tiles_m, g.tiles_n, g.group_m);
@@ -225,18 +232,13 @@ __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
   const int wm = wave >> 1, wn = wave & 1;
   const int lr = lane & 15, lg = lane >> 4;
 
-  // staging: plane blocks are contiguous (A 8 KiB, B 4 KiB per round);
-  // thread t moves A bytes [16t, 16t+16) and [4096 + 16t, ...), B bytes [16t, 16t+16)
   const int64_t rounds = g.kp / OZ_BK;
   const int64_t a_plane = g.a_rows * g.kp, b_plane = g.b_cols * g.kp;
-  const int8_t* a_src = g.a_planes + (ic.tile_row * rounds) * (OZ_BM * OZ_BK) + t * 16;
-  const int8_t* b_src = g.b_planes + (ic.tile_col * rounds) * (OZ_BN * OZ_BK) + t * 16;
-  const int a_dst0 = oz_swz(t >> 2, t & 3);         // rows 0..63
-  const int a_dst1 = oz_swz((t >> 2) + 64, t & 3);  // rows 64..127
-  const int b_dst = oz_swz(t >> 2, t & 3);
-  // operand reads: row base (a multiple of 16) + lr, chunk lg; the swizzle
-  // only depends on the row modulo 16
-  const int frag_off = oz_swz(lr, lg);
+  const int64_t rbeg = kbeg / OZ_BK;
+  // this lane's 16 bytes of fragment 0 of round 0 of the work item
+  const int8_t* a_src = g.a_planes + (ic.tile_row * rounds + rbeg) * A_BLK + lane * 16;
+  const int8_t* b_src =
+      g.b_planes + (ic.tile_col * rounds + rbeg) * B_BLK + (wn * 2) * 1024 + lane * 16;
 
   i4 acc[S][4][2];
 #pragma unroll
@@ -246,68 +248,72 @@ __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[d][i][j] = i4{0, 0, 0, 0};
 
-  i4 ra0[S], ra1[S], rb[S];
-  auto load = [&](int64_t round) {
+  // wave w moves fragments w, w + 4, ... of the stage (fragment q: slice
+  // q / 8, rows 16 (q % 8) ..)
+  auto stage_a = [&](int64_t kt, int st) {
 #pragma unroll
-    for (int u = 0; u < S; ++u) {
-      const int8_t* pa = a_src + u * a_plane + round * (OZ_BM * OZ_BK);
-      ra0[u] = *reinterpret_cast<const i4*>(pa);
-      ra1[u] = *reinterpret_cast<const i4*>(pa + 4096);
-      rb[u] = *reinterpret_cast<const i4*>(b_src + u * b_plane + round * (OZ_BN * OZ_BK));
+    for (int h = 0; h < A_FRAGS / 4; ++h) {
+      const int q = wave + 4 * h;
+      const int u = q / (A_BLK / 1024), fr = q % (A_BLK / 1024);
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(a_src + u * a_plane + kt * A_BLK + fr * 1024),
+          (lds_ptr)(lds + st * STAGE + u * A_BLK + fr * 1024), 16, 0, 0);
     }
   };
-  auto store = [&]() {
-#pragma unroll
-    for (int u = 0; u < S; ++u) {
-      *reinterpret_cast<i4*>(lds + u * A_PLANE + a_dst0) = ra0[u];
-      *reinterpret_cast<i4*>(lds + u * A_PLANE + a_dst1) = ra1[u];
-      *reinterpret_cast<i4*>(lds + S * A_PLANE + u * B_PLANE + b_dst) = rb[u];
-    }
-  };
-
-  const int64_t rbeg = kbeg / OZ_BK;
-  if (nk > 0) {
-    load(rbeg);
-    store();
-  }
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    const bool more = kt + 1 < nk;
-    if (more) load(rbeg + kt + 1);
-    i4 bfr[S][2];
+  // B fragments of the current round (bc) and of the next (bn)
+  i4 bc[S][2], bn[S][2];
+  auto load_b = [&](int64_t kt) {
 #pragma unroll
     for (int v = 0; v < S; ++v)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        bfr[v][j] = *reinterpret_cast<const i4*>(lds + S * A_PLANE + v * B_PLANE +
-                                                 (wn * 32 + j * 16) * OZ_ROW + frag_off);
-    // A fragments of slice u + 1 are read while the products of slice u run
-    const int8_t* a_frag = lds + wm * 64 * OZ_ROW + frag_off;
+        bn[v][j] = *reinterpret_cast<const i4*>(b_src + v * b_plane + kt * B_BLK + j * 1024);
+  };
+
+  if (nk > 0) {
+    stage_a(0, 0);
+    load_b(0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  // round kt computes from LDS stage kt % 2 while round kt + 1 fills the
+  // other stage and bn; the DMA writes must have landed before the barrier
+  // that opens the next round
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int st = (int)(kt & 1);
+#pragma unroll
+    for (int v = 0; v < S; ++v)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bc[v][j] = bn[v][j];
+    if (kt + 1 < nk) {
+      stage_a(kt + 1, st ^ 1);
+      load_b(kt + 1);
+    }
+    // A fragments of slice u + 1 are read while the products of slice u
+    // run: issued after its first four products, so that the wait before
+    // those covers only fragments already needed
+    const int8_t* a_frag = lds + st * STAGE + (wm * 4) * 1024 + lane * 16;
     i4 afr[2][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      afr[0][i] = *reinterpret_cast<const i4*>(a_frag + i * 16 * OZ_ROW);
+    for (int i = 0; i < 4; ++i) afr[0][i] = *reinterpret_cast<const i4*>(a_frag + i * 1024);
 #pragma unroll
     for (int u = 0; u < S; ++u) {
-      if (u + 1 < S) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          afr[(u + 1) & 1][i] =
-              *reinterpret_cast<const i4*>(a_frag + (u + 1) * A_PLANE + i * 16 * OZ_ROW);
+      for (int q = 0; q < (S - u) * 8; ++q) {
+        if (q == 4 && u + 1 < S) {
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            afr[(u + 1) & 1][i] =
+                *reinterpret_cast<const i4*>(a_frag + (u + 1) * A_BLK + i * 1024);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        const int v = q >> 3, i = (q >> 1) & 3, j = q & 1;
+        acc[u + v][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[u & 1][i], bc[v][j],
+                                                                 acc[u + v][i][j], 0, 0, 0);
       }
-#pragma unroll
-      for (int v = 0; v + u < S; ++v)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[u + v][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[u & 1][i], bfr[v][j],
-                                                                     acc[u + v][i][j], 0, 0, 0);
     }
-    if (more) {
-      __syncthreads();  // every wave has finished reading this round's stage
-      store();
-    }
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   }
 

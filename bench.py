@@ -17,12 +17,18 @@ Printed: one JSON line with the driver's keys plus
   variants      the precision and batching variants (BF16x3 vs FP32, Ozaki
                 INT8 vs FP64, batched vs single launches), each timed on its
                 own workload
+
+Timing: `--warmup` untimed steps (default 3), then `--steps` timed steps
+(default 20) with HIP events around every launch; each shape and variant
+reports its median with a distribution-free 95 % confidence interval
+(order statistics), the roofline uses the average launch duration.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -69,8 +75,10 @@ def committed_traffic(kernel_tag: str):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=20,
+                    help="timed repetitions of each variant (after min(3, reps) warm-ups)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--shapes", default="square,large_k,flat")
@@ -141,10 +149,12 @@ def main():
         ms = [a.elapsed_time(b) for a, b in events[p["name"]]]
         avg = sum(ms) / len(ms)
         tf = 2.0 * p["m"] * p["n"] * p["k"] / (avg * 1e-3) / 1e12
+        st = timing_stats(ms)
         pl = p["plan"]
         shape_rows.append(dict(
             shape=p["name"], m=p["m"], n=p["n"], k=p["k"], ms_avg=round(avg, 4),
-            ms_min=round(min(ms), 4), tflops=round(tf, 3), frac_peak=round(tf / PEAK_F64, 4),
+            ms_min=round(min(ms), 4), ms_median=st["median"], ms_ci95=st["ci95"],
+            tflops=round(tf, 3), frac_peak=round(tf / PEAK_F64, 4),
             tile=f"{pl.tile_m}x{pl.tile_n}x{pl.tile_k}", p_k=pl.p_k, group_m=pl.group_m,
             planner_q_ea_bytes=pl.q_ea_bytes, planner_q_cu_words=pl.q_cu_words,
             thm1_words=pl.thm1_words, q_cu_over_thm1=round(pl.q_cu_words / pl.thm1_words, 4)))
@@ -188,7 +198,7 @@ def main():
 
     keep = []
     if not args.no_variants:
-        out["variants"] = run_variants(torch, cm, synth, dev, stream, keep)
+        out["variants"] = run_variants(torch, cm, synth, dev, stream, keep, args.reps)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(probs, torch)
@@ -200,8 +210,29 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def _time(torch, stream, fn, reps):
-    fn()
+def timing_stats(ms):
+    """Median of the samples with a distribution-free 95 % confidence
+    interval: order statistics x_(j) .. x_(n+1-j), j the largest index with
+    P(Bin(n, 1/2) <= j - 1) <= 0.025 (the whole range when n < 6)."""
+    xs = sorted(ms)
+    n = len(xs)
+    cdf, j = 0.0, 0
+    while j < n:
+        p = math.comb(n, j) / 2.0 ** n
+        if cdf + p > 0.025:
+            break
+        cdf += p
+        j += 1
+    j = max(j, 1)
+    med = xs[n // 2] if n % 2 else 0.5 * (xs[n // 2 - 1] + xs[n // 2])
+    return {"median": round(med, 4), "ci95": [round(xs[j - 1], 4), round(xs[n - j], 4)], "n": n}
+
+
+def _time(torch, stream, fn, reps=20, warm=3):
+    """Median time of fn (HIP events on `stream`, one synchronisation per
+    repetition) after `warm` untimed calls; returns (median_ms, stats)."""
+    for _ in range(warm):
+        fn()
     torch.cuda.synchronize()
     ts = []
     for _ in range(reps):
@@ -212,11 +243,11 @@ def _time(torch, stream, fn, reps):
         e1.record(stream)
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1))
-    ts.sort()
-    return ts[len(ts) // 2]
+    st = timing_stats(ts)
+    return st["median"], st
 
 
-def run_variants(torch, cm, synth, dev, stream, keep):
+def run_variants(torch, cm, synth, dev, stream, keep, reps=20):
     """Precision and batching variants, each on its own workload:
     BF16x3 vs native FP32 (16384^3 and 4096^2 x 2^18, uniform FP32),
     Ozaki INT8 slices vs native FP64 (8192^3, sign*U[1,2)*2^e, e in [-20,20]),
@@ -234,13 +265,15 @@ def run_variants(torch, cm, synth, dev, stream, keep):
             C = torch.empty((m, n), dtype=torch.float32, device=dev)
             rc, plan = cm.cosma_plan_query(m, n, k, dt)
             cm.ensure_workspace(plan.workspace_bytes)
-            ms = _time(torch, stream, lambda: cm.gemm(A, B, C, dtype=dt, stream=stream), 3)
-            res[dt] = (ms, 2.0 * m * n * k / (ms * 1e-3) / 1e12, plan)
+            ms, st = _time(torch, stream, lambda: cm.gemm(A, B, C, dtype=dt, stream=stream),
+                           reps, min(3, reps))
+            res[dt] = (ms, 2.0 * m * n * k / (ms * 1e-3) / 1e12, plan, st["ci95"])
             keep.append((f"{dt} {m}x{n}x{k}", C, m, n, k, synth.UNIFORM_F32, "f32"))
         f32, x3 = res["f32"], res["bf16x3"]
-        rows.append({"shape": f"{m}x{n}x{k}", "f32_ms": round(f32[0], 3),
+        rows.append({"shape": f"{m}x{n}x{k}", "f32_ms": round(f32[0], 3), "f32_ms_ci95": f32[3],
                      "f32_tflops": round(f32[1], 2), "f32_frac_peak": round(f32[1] / PEAK_F32, 4),
-                     "bf16x3_ms": round(x3[0], 3), "bf16x3_tflops": round(x3[1], 2),
+                     "bf16x3_ms": round(x3[0], 3), "bf16x3_ms_ci95": x3[3],
+                     "bf16x3_tflops": round(x3[1], 2),
                      "bf16x3_frac_bf16_peak": round(3 * x3[1] / PEAK_BF16, 4),
                      "bf16x3_tile": f"{x3[2].tile_m}x{x3[2].tile_n}",
                      "speedup_vs_f32": round(f32[0] / x3[0], 3)})
@@ -257,15 +290,18 @@ def run_variants(torch, cm, synth, dev, stream, keep):
         C = torch.empty((m, n), dtype=torch.float64, device=dev)
         rc, plan = cm.cosma_plan_query(m, n, k, dt)
         cm.ensure_workspace(plan.workspace_bytes)
-        ms = _time(torch, stream, lambda: cm.gemm(A, B, C, dtype=dt, stream=stream), 5)
-        res[dt] = (ms, 2.0 * m * n * k / (ms * 1e-3) / 1e12, plan)
+        ms, st = _time(torch, stream, lambda: cm.gemm(A, B, C, dtype=dt, stream=stream),
+                           reps, min(3, reps))
+        res[dt] = (ms, 2.0 * m * n * k / (ms * 1e-3) / 1e12, plan, st["ci95"])
         keep.append((f"{dt} {m}^3 wide", C, m, n, k, synth.WIDE_F64, "f64"))
     s_ = res["ozaki"][2].slices
     out["ozaki_vs_f64"] = {
         "shape": "8192^3, sign*U[1,2)*2^e, e in [-20,20]", "slices": s_,
         "int8_products": s_ * (s_ + 1) // 2,
-        "f64_ms": round(res["f64"][0], 3), "f64_tflops": round(res["f64"][1], 2),
-        "ozaki_ms": round(res["ozaki"][0], 3), "ozaki_tflops": round(res["ozaki"][1], 2),
+        "f64_ms": round(res["f64"][0], 3), "f64_ms_ci95": res["f64"][3],
+        "f64_tflops": round(res["f64"][1], 2),
+        "ozaki_ms": round(res["ozaki"][0], 3), "ozaki_ms_ci95": res["ozaki"][3],
+        "ozaki_tflops": round(res["ozaki"][1], 2),
         "ozaki_frac_int8_peak": round(res["ozaki"][1] * s_ * (s_ + 1) / 2 / PEAK_I8, 4),
         "speedup_vs_f64": round(res["f64"][0] / res["ozaki"][0], 3)}
     del A, B
@@ -286,7 +322,8 @@ def run_variants(torch, cm, synth, dev, stream, keep):
     rc, h = cm.cosma_batch_create(*args, cm.COSMA_F32, stream)
     cm.check(rc, "cosma_batch_create")
     rc, policy, groups, items, pol_ms = cm.cosma_batch_info(h)
-    t_graph = _time(torch, stream, lambda: cm.cosma_batch_run(h, stream), 5)
+    t_graph, st_graph = _time(torch, stream, lambda: cm.cosma_batch_run(h, stream), reps,
+                                min(3, reps))
     ws = max(cm.cosma_workspace_size(a, b, c, cm.COSMA_F32)[1] for a, b, c in dims)
     cm.ensure_workspace(ws)
 
@@ -294,15 +331,15 @@ def run_variants(torch, cm, synth, dev, stream, keep):
         for i, (bm, bn, bk) in enumerate(dims):
             cm.cosma_gemm(bm, bn, bk, 1.0, mats[i][0], bk, mats[i][1], bn, 0.0, mats[i][2], bn,
                           cm.COSMA_F32, stream)
-    t_loop = _time(torch, stream, loop, 3)
+    t_loop, st_loop = _time(torch, stream, loop, reps, min(3, reps))
     cm.cosma_batch_run(h, stream)  # final results come from the graph
     torch.cuda.synchronize()
     cm.cosma_batch_destroy(h)
     out["batched_512_f32"] = {
         "problems": 512, "dims": "m,n,k log-uniform in [64,4096], seeded per problem",
-        "sum_2mnk": flops, "graph_ms": round(t_graph, 3),
+        "sum_2mnk": flops, "graph_ms": round(t_graph, 3), "graph_ms_ci95": st_graph["ci95"],
         "graph_tflops": round(flops / (t_graph * 1e-3) / 1e12, 2),
-        "loop_of_single_launches_ms": round(t_loop, 3),
+        "loop_of_single_launches_ms": round(t_loop, 3), "loop_ms_ci95": st_loop["ci95"],
         "loop_tflops": round(flops / (t_loop * 1e-3) / 1e12, 2),
         "speedup_vs_loop": round(t_loop / t_graph, 3), "autotuned_policy": policy,
         "policy_candidates_ms": [round(x, 3) for x in pol_ms], "persistent_launches": groups,

@@ -303,44 +303,113 @@ __device__ __forceinline__ void split8(const float (&x)[8], us8& hi, us8& lo) {
 // contiguous block and the GEMM needs no bounds checks on its loads.
 constexpr int X3_ROWS = 256, X3_COLS = 128, X3_K = 32;
 
-// A: thread per (row, 8 consecutive k); four threads cover one row's round.
+// A: one block per 16 rows x 256 k (8 rounds).  The FP32 values are read as
+// 1 KiB row segments (one wave instruction per row) into LDS, then every
+// round's 16 rows x 32 k are split and written as 1 KiB contiguous runs of
+// each plane.  LDS rows are padded to 260 floats so that the second phase's
+// 16-byte reads (8 lanes = 2 rows x 4 chunks) touch distinct bank quads.
+constexpr int XA_ROWS = 16, XA_K = 256, XA_LD = XA_K + 4;
+
 __global__ __launch_bounds__(256) void x3_split_a_kernel(const float* __restrict__ A, int64_t m,
-                                                         int64_t k, int64_t lda, int64_t rows_p,
-                                                         int64_t kp, unsigned short* __restrict__ hi,
+                                                         int64_t k, int64_t lda, int vec,
+                                                         int64_t rows_p, int64_t kp,
+                                                         unsigned short* __restrict__ hi,
                                                          unsigned short* __restrict__ lo) {
-  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t per_round = rows_p * 4;
-  if (id >= per_round * (kp / X3_K)) return;
-  const int64_t round = id / per_round, rem = id - round * per_round;
-  const int64_t row = rem / 4, kc = round * X3_K + (rem % 4) * 8;
-  float x[8];
+  __shared__ __attribute__((aligned(16))) float tile[XA_ROWS * XA_LD];
+  const int64_t kblocks = ceil_div(kp, (int64_t)XA_K);
+  const int64_t row0 = ((int64_t)blockIdx.x / kblocks) * XA_ROWS;
+  const int64_t k0 = ((int64_t)blockIdx.x % kblocks) * XA_K;
+  const int t = threadIdx.x;
 #pragma unroll
-  for (int e = 0; e < 8; ++e)
-    x[e] = (row < m && kc + e < k) ? A[row * lda + kc + e] : 0.0f;
-  us8 h, l;
-  split8(x, h, l);
-  const int64_t off = (round * rows_p + row) * X3_K + (rem % 4) * 8;
-  *reinterpret_cast<us8*>(hi + off) = h;
-  *reinterpret_cast<us8*>(lo + off) = l;
+  for (int i = 0; i < 4; ++i) {
+    const int q = t + 256 * i;  // float4 index: row q / 64, k 4 (q % 64)
+    const int r = q >> 6, c = (q & 63) * 4;
+    const int64_t row = row0 + r, kk = k0 + c;
+    f4 x = f4{0.f, 0.f, 0.f, 0.f};
+    if (row < m) {
+      const float* src = A + row * lda + kk;
+      if (vec && kk + 4 <= k) {
+        x = *reinterpret_cast<const f4*>(src);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (kk + e < k) x[e] = src[e];
+      }
+    }
+    *reinterpret_cast<f4*>(tile + r * XA_LD + c) = x;
+  }
+  __syncthreads();
+  const int64_t rounds = kp / X3_K;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = t + 256 * h;  // 8-value chunk: round c / 64, row (c % 64) / 4, k chunk c % 4
+    const int rr = c >> 6, r = (c & 63) >> 2, kc = c & 3;
+    const int64_t round = k0 / X3_K + rr;
+    if (round < rounds) {
+      const float* src = tile + r * XA_LD + rr * X3_K + kc * 8;
+      const f4 x0 = *reinterpret_cast<const f4*>(src);
+      const f4 x1 = *reinterpret_cast<const f4*>(src + 4);
+      const float x[8] = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
+      us8 hv, lv;
+      split8(x, hv, lv);
+      const int64_t off = (round * rows_p + row0 + r) * X3_K + kc * 8;
+      *reinterpret_cast<us8*>(hi + off) = hv;
+      *reinterpret_cast<us8*>(lo + off) = lv;
+    }
+  }
 }
 
-// B: thread per (column, 8 consecutive k), columns fastest across the wave.
+// B: one block per round (32 k) x 128 columns.  The 32 rows are read as
+// 512-byte segments into LDS, then every column's 32 k are split and written
+// (16 columns x 64 bytes = 1 KiB contiguous per wave and plane).  LDS rows
+// are 130 floats apart, so the column reads of a wave (16 columns x 4 k
+// chunks) fall into 64 distinct banks.
+constexpr int XB_COLS = 128, XB_LD = XB_COLS + 2;
+
 __global__ __launch_bounds__(256) void x3_split_b_kernel(const float* __restrict__ B, int64_t k,
-                                                         int64_t n, int64_t ldb, int64_t cols_p,
-                                                         int64_t kp, unsigned short* __restrict__ hi,
+                                                         int64_t n, int64_t ldb, int vec,
+                                                         int64_t cols_p, int64_t kp,
+                                                         unsigned short* __restrict__ hi,
                                                          unsigned short* __restrict__ lo) {
-  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (id >= cols_p * (kp / 8)) return;
-  const int64_t kc = (id / cols_p) * 8, col = id % cols_p;
-  float x[8];
+  __shared__ __attribute__((aligned(16))) float tile[X3_K * XB_LD];
+  const int64_t cblocks = cols_p / XB_COLS;
+  const int64_t round = (int64_t)blockIdx.x / cblocks;
+  const int64_t col0 = ((int64_t)blockIdx.x % cblocks) * XB_COLS;
+  const int t = threadIdx.x;
 #pragma unroll
-  for (int e = 0; e < 8; ++e)
-    x[e] = (col < n && kc + e < k) ? B[(kc + e) * ldb + col] : 0.0f;
-  us8 h, l;
-  split8(x, h, l);
-  const int64_t off = ((kc / X3_K) * cols_p + col) * X3_K + kc % X3_K;
-  *reinterpret_cast<us8*>(hi + off) = h;
-  *reinterpret_cast<us8*>(lo + off) = l;
+  for (int i = 0; i < 4; ++i) {
+    const int q = t + 256 * i;  // float4 index: k row q / 32, columns 4 (q % 32)
+    const int r = q >> 5, c = (q & 31) * 4;
+    const int64_t kk = round * X3_K + r, col = col0 + c;
+    f4 x = f4{0.f, 0.f, 0.f, 0.f};
+    if (kk < k) {
+      const float* src = B + kk * ldb + col;
+      if (vec && col + 4 <= n) {
+        x = *reinterpret_cast<const f4*>(src);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (col + e < n) x[e] = src[e];
+      }
+    }
+    float* dst = tile + r * XB_LD + c;  // 8-byte aligned (XB_LD is even)
+    *reinterpret_cast<float2*>(dst) = float2{x[0], x[1]};
+    *reinterpret_cast<float2*>(dst + 2) = float2{x[2], x[3]};
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = t + 256 * h;  // 8-value chunk: column c / 4, k chunk c % 4
+    const int cc = c >> 2, kc = c & 3;
+    float x[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = tile[(kc * 8 + e) * XB_LD + cc];
+    us8 hv, lv;
+    split8(x, hv, lv);
+    const int64_t off = (round * cols_p + col0 + cc) * X3_K + kc * 8;
+    *reinterpret_cast<us8*>(hi + off) = hv;
+    *reinterpret_cast<us8*>(lo + off) = lv;
+  }
 }
 
 // GEMM on the split planes.  Staging per round: the tile's A_hi, A_lo
@@ -549,13 +618,20 @@ hipError_t launch_x3(K kernel, int threads, const X3Args& g, hipStream_t s) {
 
 hipError_t launch_bf16x3_split(const float* A, int64_t m, int64_t k, int64_t lda, const float* B,
                                int64_t n, int64_t ldb, const X3Args& g, hipStream_t s) {
-  const int64_t ta = g.rows_p * 4 * (g.kp / X3_K), tb = g.cols_p * (g.kp / 8);
-  hipLaunchKernelGGL(x3_split_a_kernel, dim3((unsigned)((ta + 255) / 256)), dim3(256), 0, s, A, m,
-                     k, lda, g.rows_p, g.kp, const_cast<unsigned short*>(g.a_hi),
-                     const_cast<unsigned short*>(g.a_lo));
-  hipLaunchKernelGGL(x3_split_b_kernel, dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, s, B, k,
-                     n, ldb, g.cols_p, g.kp, const_cast<unsigned short*>(g.b_hi),
-                     const_cast<unsigned short*>(g.b_lo));
+  if (g.rows_p % XA_ROWS || g.cols_p % XB_COLS || g.kp % X3_K) return hipErrorInvalidValue;
+  const int64_t ba = (g.rows_p / XA_ROWS) * ceil_div(g.kp, (int64_t)XA_K);
+  const int64_t bb = (g.kp / X3_K) * (g.cols_p / XB_COLS);
+  if (ba > 0x7fffffffLL || bb > 0x7fffffffLL) return hipErrorInvalidValue;
+  const int vec_a = (reinterpret_cast<uintptr_t>(A) % 16 == 0 && lda % 4 == 0) ? 1 : 0;
+  const int vec_b = (reinterpret_cast<uintptr_t>(B) % 16 == 0 && ldb % 4 == 0) ? 1 : 0;
+  if (ba > 0)
+    hipLaunchKernelGGL(x3_split_a_kernel, dim3((unsigned)ba), dim3(256), 0, s, A, m, k, lda, vec_a,
+                       g.rows_p, g.kp, const_cast<unsigned short*>(g.a_hi),
+                       const_cast<unsigned short*>(g.a_lo));
+  if (bb > 0)
+    hipLaunchKernelGGL(x3_split_b_kernel, dim3((unsigned)bb), dim3(256), 0, s, B, k, n, ldb, vec_b,
+                       g.cols_p, g.kp, const_cast<unsigned short*>(g.b_hi),
+                       const_cast<unsigned short*>(g.b_lo));
   return hipGetLastError();
 }
 

@@ -278,9 +278,15 @@ struct X3Tile {
   static_assert(2 * STAGE * 2 <= 160 * 1024, "LDS budget");
 };
 
-// Offset (in bf16) of 16-byte chunk `chunk` of LDS row `row`.
+// Position of 16-byte chunk `chunk` (k % 32 in [8 chunk, 8 chunk + 8)) inside
+// the 64-byte row `row` of a plane, and the offset (in bf16) of that chunk in
+// a staged block whose rows start at a multiple of 16 (the swizzle depends on
+// the row modulo 16 only, so planes and LDS blocks share it).
+__device__ __forceinline__ int x3_chunk(int64_t row, int chunk) {
+  return (int)((chunk ^ row ^ (row >> 2)) & 3);
+}
 __device__ __forceinline__ int x3_off(int row, int chunk) {
-  return row * 32 + ((chunk ^ row ^ (row >> 2)) & 3) * 8;
+  return row * 32 + x3_chunk(row, chunk) * 8;
 }
 
 // Round-to-nearest-even split of 8 floats into bf16 hi and lo pieces.
@@ -296,12 +302,14 @@ __device__ __forceinline__ void split8(const float (&x)[8], us8& hi, us8& lo) {
 }
 
 // Split pass: FP32 operands -> bf16 hi / lo planes in the GEMM's staging
-// order.  A plane: element (row, k) at ((k / 32) * rows_p + row) * 32 + k % 32
-// (rows_p = rows padded to X3_ROWS); B planes are stored transposed,
-// (col, k) at ((k / 32) * cols_p + col) * 32 + k % 32.  Padding rows,
-// columns and k hold zeros, so a tile's round of any tile shape is one
-// contiguous block and the GEMM needs no bounds checks on its loads.
-constexpr int X3_ROWS = 256, X3_COLS = 128, X3_K = 32;
+// order.  A plane: element (row, k) at
+//   ((k / 32) * rows_p + row) * 32 + x3_chunk(row, (k % 32) / 8) * 8 + k % 8
+// (rows_p = rows padded to 256, the tallest tile); B planes are stored
+// transposed, (col, k)
+// likewise with cols_p.  Padding rows, columns and k hold zeros, so a tile's
+// round of any tile shape is one contiguous block, already in the swizzled
+// layout the GEMM's LDS uses, and the GEMM copies it with no bounds checks.
+constexpr int X3_K = 32;
 
 // A: one block per 16 rows x 256 k (8 rounds).  The FP32 values are read as
 // 1 KiB row segments (one wave instruction per row) into LDS, then every
@@ -352,7 +360,8 @@ __global__ __launch_bounds__(256) void x3_split_a_kernel(const float* __restrict
       const float x[8] = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
       us8 hv, lv;
       split8(x, hv, lv);
-      const int64_t off = (round * rows_p + row0 + r) * X3_K + kc * 8;
+      const int64_t row = row0 + r;
+      const int64_t off = (round * rows_p + row) * X3_K + x3_chunk(row, kc) * 8;
       *reinterpret_cast<us8*>(hi + off) = hv;
       *reinterpret_cast<us8*>(lo + off) = lv;
     }
@@ -406,28 +415,30 @@ __global__ __launch_bounds__(256) void x3_split_b_kernel(const float* __restrict
     for (int e = 0; e < 8; ++e) x[e] = tile[(kc * 8 + e) * XB_LD + cc];
     us8 hv, lv;
     split8(x, hv, lv);
-    const int64_t off = (round * cols_p + col0 + cc) * X3_K + kc * 8;
+    const int64_t col = col0 + cc;
+    const int64_t off = (round * cols_p + col) * X3_K + x3_chunk(col, kc) * 8;
     *reinterpret_cast<us8*>(hi + off) = hv;
     *reinterpret_cast<us8*>(lo + off) = lv;
   }
 }
 
-// GEMM on the split planes.  Staging per round: the tile's A_hi, A_lo
-// (BM rows x 64 bytes each) and B_hi, B_lo (BN columns x 64 bytes) blocks
-// are contiguous; thread t copies 16-byte chunks c = t + NT*i, chunk c of a
-// block being row c / 4, k chunk c % 4, into the swizzled LDS rows.
-template <class TL, int BM, int BN>
-struct X3Stage {
-  static constexpr int A_LD = BM * 4 / TL::NT;  // 16-byte chunks per thread per A plane
-  static constexpr int B_LD = BN * 4 / TL::NT;
-  static_assert(BM * 4 % TL::NT == 0 && BN * 4 % TL::NT == 0, "staging map");
-};
+// GEMM on the split planes.  A round's A_hi, A_lo (BM rows x 64 bytes each)
+// and B_hi, B_lo (BN columns x 64 bytes) blocks are contiguous and already
+// swizzled, so staging is a copy of 1 KiB pieces by 16-byte global-to-LDS
+// DMA (no registers, no LDS write instructions).  NS LDS stages form a ring:
+// the DMA of round r + NS - 1 is issued at the start of round r.
+typedef __attribute__((address_space(3))) void* lds_ptr;
 
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int BK, int WM, int WN, int NS>
 __global__ __launch_bounds__(WM* WN * 64) void gemm_bf16x3_kernel(X3Args g) {
   using TL = X3Tile<BM, BN, BK, WM, WN>;
-  using SM = X3Stage<TL, BM, BN>;
-  __shared__ __attribute__((aligned(16))) unsigned short lds[2][TL::STAGE];
+  constexpr int NW = WM * WN;
+  constexpr int A_CH = BM * 64 / 1024, B_CH = BN * 64 / 1024;  // 1 KiB pieces per plane
+  static_assert(A_CH % NW == 0 && B_CH % NW == 0, "every wave moves whole pieces of each plane");
+  constexpr int A_PW = A_CH / NW, B_PW = B_CH / NW;
+  constexpr int DMA_PW = 2 * (A_PW + B_PW);  // DMA instructions per wave and round
+  static_assert(NS * TL::STAGE * 2 <= 160 * 1024, "LDS budget");
+  __shared__ __attribute__((aligned(1024))) unsigned short lds[NS * TL::STAGE];
 
   const int64_t l = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x, g.num_xcds);
   const ItemCoord ic = item_coord(l, g.tiles_m, g.tiles_n, g.group_m);
@@ -446,48 +457,33 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_bf16x3_kernel(X3Args g) {
 #pragma unroll
     for (int j = 0; j < TL::NI; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  // per-thread sources (bf16 units) of round 0 of this item, and LDS targets
+  // this lane's 16 bytes of piece 0 of round 0 of the item, per plane (bf16 units)
   const int64_t a_step = g.rows_p * X3_K, b_step = g.cols_p * X3_K;  // one round further
-  const unsigned short* a_hi_src = g.a_hi + (kbeg / X3_K) * a_step + row0 * X3_K;
-  const unsigned short* a_lo_src = g.a_lo + (kbeg / X3_K) * a_step + row0 * X3_K;
-  const unsigned short* b_hi_src = g.b_hi + (kbeg / X3_K) * b_step + col0 * X3_K;
-  const unsigned short* b_lo_src = g.b_lo + (kbeg / X3_K) * b_step + col0 * X3_K;
-  // two register sets: the loads of round r + 2 are issued at the start of
-  // round r and reach LDS at the end of round r + 1 (two rounds of latency
-  // hiding), while LDS holds rounds r and r + 1
-  us8 ra_h[2][SM::A_LD], ra_l[2][SM::A_LD], rb_h[2][SM::B_LD], rb_l[2][SM::B_LD];
-  auto load = [&](int set, int64_t round) {
+  const int64_t a0 = (kbeg / X3_K) * a_step + row0 * X3_K + lane * 8;
+  const int64_t b0 = (kbeg / X3_K) * b_step + col0 * X3_K + lane * 8;
+  const unsigned short* a_hi_src = g.a_hi + a0;
+  const unsigned short* a_lo_src = g.a_lo + a0;
+  const unsigned short* b_hi_src = g.b_hi + b0;
+  const unsigned short* b_lo_src = g.b_lo + b0;
+  // wave w moves pieces w, w + NW, ... of every plane
+  auto stage_in = [&](int64_t round, int st) {
+    unsigned short* base = lds + st * TL::STAGE;
 #pragma unroll
-    for (int i = 0; i < SM::A_LD; ++i) {
-      const int64_t o = round * a_step + (t + TL::NT * i) * 8;
-      ra_h[set][i] = *reinterpret_cast<const us8*>(a_hi_src + o);
-      ra_l[set][i] = *reinterpret_cast<const us8*>(a_lo_src + o);
+    for (int h = 0; h < A_PW; ++h) {
+      const int c = (wave + NW * h) * 512;
+      __builtin_amdgcn_global_load_lds((const void*)(a_hi_src + round * a_step + c),
+                                       (lds_ptr)(base + c), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(a_lo_src + round * a_step + c),
+                                       (lds_ptr)(base + TL::A_PLANE + c), 16, 0, 0);
     }
 #pragma unroll
-    for (int i = 0; i < SM::B_LD; ++i) {
-      const int64_t o = round * b_step + (t + TL::NT * i) * 8;
-      rb_h[set][i] = *reinterpret_cast<const us8*>(b_hi_src + o);
-      rb_l[set][i] = *reinterpret_cast<const us8*>(b_lo_src + o);
-    }
-  };
-  auto store = [&](int set, unsigned short* st) {
-    unsigned short* a_hi = st;
-    unsigned short* a_lo = st + TL::A_PLANE;
-    unsigned short* b_hi = st + 2 * TL::A_PLANE;
-    unsigned short* b_lo = st + 2 * TL::A_PLANE + TL::B_PLANE;
-#pragma unroll
-    for (int i = 0; i < SM::A_LD; ++i) {
-      const int c = t + TL::NT * i;
-      const int o = x3_off(c >> 2, c & 3);
-      *reinterpret_cast<us8*>(a_hi + o) = ra_h[set][i];
-      *reinterpret_cast<us8*>(a_lo + o) = ra_l[set][i];
-    }
-#pragma unroll
-    for (int i = 0; i < SM::B_LD; ++i) {
-      const int c = t + TL::NT * i;
-      const int o = x3_off(c >> 2, c & 3);
-      *reinterpret_cast<us8*>(b_hi + o) = rb_h[set][i];
-      *reinterpret_cast<us8*>(b_lo + o) = rb_l[set][i];
+    for (int h = 0; h < B_PW; ++h) {
+      const int c = (wave + NW * h) * 512;
+      __builtin_amdgcn_global_load_lds((const void*)(b_hi_src + round * b_step + c),
+                                       (lds_ptr)(base + 2 * TL::A_PLANE + c), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(b_lo_src + round * b_step + c),
+                                       (lds_ptr)(base + 2 * TL::A_PLANE + TL::B_PLANE + c), 16, 0,
+                                       0);
     }
   };
   const int frag = x3_off(lr, lg);
@@ -519,28 +515,27 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_bf16x3_kernel(X3Args g) {
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
       }
   };
-  // one round: prefetch round kt + 2 into `set`, compute round kt from LDS
-  // stage kt % 2 (== set), store round kt + 1 (register set 1 - set) into
-  // the other stage
-  auto round_step = [&](int set, int64_t kt) {
-    if (kt + 2 < nk) load(set, kt + 2);
-    compute(lds[set]);
-    if (kt + 1 < nk) store(1 - set, lds[1 - set]);
-    __syncthreads();
-  };
-
-  if (nk > 0) {
-    load(0, 0);
-    if (nk > 1) load(1, 1);
-    store(0, lds[0]);
-  }
+  // round kt computes from stage kt % NS while the DMA of round kt + NS - 1
+  // fills the stage that round kt - 1 used; before the barrier that opens
+  // round kt + 1, that round's pieces (issued NS - 2 rounds earlier) must
+  // have landed, which leaves this round's DMA_PW instructions in flight
+  for (int r = 0; r < NS - 1; ++r)
+    if (r < nk) stage_in(r, r);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  int64_t kt = 0;
-  for (; kt + 1 < nk; kt += 2) {
-    round_step(0, kt);
-    round_step(1, kt + 1);
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const bool issue = kt + NS - 1 < nk;
+    if (issue) stage_in(kt + NS - 1, (int)((kt + NS - 1) % NS));
+    compute(lds + (int)(kt % NS) * TL::STAGE);
+    if (NS > 2 && issue) {
+      static_assert(DMA_PW <= 15, "vmcnt immediate");
+      // vmcnt(DMA_PW): bits 3:0, expcnt and lgkmcnt left at their maximum
+      __builtin_amdgcn_s_waitcnt((NS > 2 ? DMA_PW : 0) | 0x0F70);
+    } else {
+      __builtin_amdgcn_s_waitcnt(0);
+    }
+    __syncthreads();
   }
-  if (kt < nk) round_step(0, kt);
   GemmArgs e;
   e.C = g.C;
   e.P = g.P;
@@ -637,9 +632,9 @@ hipError_t launch_bf16x3_split(const float* A, int64_t m, int64_t k, int64_t lda
 
 hipError_t launch_gemm_bf16x3(int tile_id, const X3Args& g, hipStream_t s) {
   switch (tile_id) {
-    case 0: return launch_x3(gemm_bf16x3_kernel<128, 128, 32, 2, 2>, 256, g, s);
-    case 1: return launch_x3(gemm_bf16x3_kernel<64, 64, 32, 2, 2>, 256, g, s);
-    case 2: return launch_x3(gemm_bf16x3_kernel<256, 128, 32, 4, 2>, 512, g, s);
+    case 0: return launch_x3(gemm_bf16x3_kernel<128, 128, 32, 2, 2, 2>, 256, g, s);
+    case 1: return launch_x3(gemm_bf16x3_kernel<64, 64, 32, 2, 2, 2>, 256, g, s);
+    case 2: return launch_x3(gemm_bf16x3_kernel<256, 128, 32, 4, 2, 2>, 512, g, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -36,9 +36,9 @@ constexpr TileDesc kTilesF32[] = {
     {256, 128, 32, 512, 1, 0.85},
 };
 constexpr TileDesc kTilesBf16x3[] = {
-    {128, 128, 32, 256, 2, 0.50},
+    {128, 128, 32, 256, 2, 0.48},
     {64, 64, 32, 256, 4, 0.35},
-    {256, 128, 32, 512, 1, 0.55},
+    {256, 128, 32, 512, 1, 0.45},
 };
 constexpr TileDesc kTilesOzaki[] = {
     {128, 64, 64, 256, 1, 0.60},

@@ -187,8 +187,10 @@ __global__ __launch_bounds__(256) void slice_b_kernel(const double* __restrict__
 }
 
 // ---------------------------------------------------------------- GEMM
-// Work item: a 128 x 64 block of C, 4 waves of 64 x 32 (4 x 2 blocks of
-// 16 x 16), v_mfma_i32_16x16x64_i8: lane l (r = l % 16, g = l / 16)
+// Work item: a 128 x 64 block of C; up to s = 7, 8 waves (two per SIMD) of
+// 64 x 16, for s = 8 (whose accumulators need more registers) 4 waves of
+// 64 x 32; blocks of 16 x 16 on v_mfma_i32_16x16x64_i8: lane l (r = l % 16,
+// g = l / 16)
 // supplies A[r][16g .. 16g+15] and B[16g .. 16g+15][r] and holds
 // D[4g + v][r] in element v.  One round = 64 k.
 //
@@ -196,8 +198,12 @@ __global__ __launch_bounds__(256) void slice_b_kernel(const double* __restrict__
 // by 16-byte global-to-LDS DMA (no registers, no conversion: the planes are
 // already fragments, and each wave instruction moves one 1 KiB fragment);
 // the next round's stage fills while the MFMAs run on the current one.  The
-// two B fragments of each plane that a wave needs are loaded straight into
+// B fragments of each plane that a wave needs are loaded straight into
 // registers one round ahead.  LDS per block: 2 s 8 KiB (112 KiB at s = 7).
+template <int S>
+constexpr int oz_waves() {
+  return S <= 7 ? 8 : 4;
+}
 typedef __attribute__((address_space(3))) void* lds_ptr;
 
 struct OzArgs {
@@ -215,11 +221,14 @@ struct OzArgs {
 };
 
 template <int S>
-__global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
+__global__ __launch_bounds__(oz_waves<S>() * 64) void ozaki_gemm_kernel(OzArgs g) {
+  constexpr int OZ_WAVES = oz_waves<S>();
+  constexpr int WN = OZ_WAVES / 2;       // waves along n (2 along m)
+  constexpr int NJ = OZ_BN / 16 / WN;    // 16-column blocks per wave
   constexpr int A_BLK = OZ_BM * OZ_BK, B_BLK = OZ_BN * OZ_BK;
   constexpr int STAGE = S * A_BLK;
   constexpr int A_FRAGS = S * (A_BLK / 1024);  // 1 KiB fragments per stage
-  static_assert(A_FRAGS % 4 == 0, "fragments per wave");
+  static_assert(A_FRAGS % OZ_WAVES == 0, "fragments per wave");
   __shared__ __attribute__((aligned(1024))) int8_t lds[2 * STAGE];
 
   const int64_t l = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x, g.num_xcds);
@@ -229,7 +238,7 @@ __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
   const int64_t kend = min64(g.k, kbeg + g.k_split);
   const int64_t nk = ceil_div(kend - kbeg, OZ_BK);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;  // rows 64 wm .., columns 16 NJ wn ..
   const int lr = lane & 15, lg = lane >> 4;
 
   const int64_t rounds = g.kp / OZ_BK;
@@ -238,22 +247,22 @@ __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
   // this lane's 16 bytes of fragment 0 of round 0 of the work item
   const int8_t* a_src = g.a_planes + (ic.tile_row * rounds + rbeg) * A_BLK + lane * 16;
   const int8_t* b_src =
-      g.b_planes + (ic.tile_col * rounds + rbeg) * B_BLK + (wn * 2) * 1024 + lane * 16;
+      g.b_planes + (ic.tile_col * rounds + rbeg) * B_BLK + wn * NJ * 1024 + lane * 16;
 
-  i4 acc[S][4][2];
+  i4 acc[S][4][NJ];
 #pragma unroll
   for (int d = 0; d < S; ++d)
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[d][i][j] = i4{0, 0, 0, 0};
+      for (int j = 0; j < NJ; ++j) acc[d][i][j] = i4{0, 0, 0, 0};
 
-  // wave w moves fragments w, w + 4, ... of the stage (fragment q: slice
-  // q / 8, rows 16 (q % 8) ..)
+  // wave w moves fragments w, w + OZ_WAVES, ... of the stage (fragment q:
+  // slice q / 8, rows 16 (q % 8) ..)
   auto stage_a = [&](int64_t kt, int st) {
 #pragma unroll
-    for (int h = 0; h < A_FRAGS / 4; ++h) {
-      const int q = wave + 4 * h;
+    for (int h = 0; h < A_FRAGS / OZ_WAVES; ++h) {
+      const int q = wave + OZ_WAVES * h;
       const int u = q / (A_BLK / 1024), fr = q % (A_BLK / 1024);
       __builtin_amdgcn_global_load_lds(
           (const void*)(a_src + u * a_plane + kt * A_BLK + fr * 1024),
@@ -261,12 +270,12 @@ __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
     }
   };
   // B fragments of the current round (bc) and of the next (bn)
-  i4 bc[S][2], bn[S][2];
+  i4 bc[S][NJ], bn[S][NJ];
   auto load_b = [&](int64_t kt) {
 #pragma unroll
     for (int v = 0; v < S; ++v)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NJ; ++j)
         bn[v][j] = *reinterpret_cast<const i4*>(b_src + v * b_plane + kt * B_BLK + j * 1024);
   };
 
@@ -284,13 +293,13 @@ __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
 #pragma unroll
     for (int v = 0; v < S; ++v)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bc[v][j] = bn[v][j];
+      for (int j = 0; j < NJ; ++j) bc[v][j] = bn[v][j];
     if (kt + 1 < nk) {
       stage_a(kt + 1, st ^ 1);
       load_b(kt + 1);
     }
     // A fragments of slice u + 1 are read while the products of slice u
-    // run: issued after its first four products, so that the wait before
+    // run: issued after its first two products, so that the wait before
     // those covers only fragments already needed
     const int8_t* a_frag = lds + st * STAGE + (wm * 4) * 1024 + lane * 16;
     i4 afr[2][4];
@@ -299,8 +308,8 @@ __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
 #pragma unroll
     for (int u = 0; u < S; ++u) {
 #pragma unroll
-      for (int q = 0; q < (S - u) * 8; ++q) {
-        if (q == 4 && u + 1 < S) {
+      for (int q = 0; q < (S - u) * 4 * NJ; ++q) {
+        if (q == 2 && u + 1 < S) {
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int i = 0; i < 4; ++i)
@@ -308,7 +317,7 @@ __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
                 *reinterpret_cast<const i4*>(a_frag + (u + 1) * A_BLK + i * 1024);
           __builtin_amdgcn_sched_barrier(0);
         }
-        const int v = q >> 3, i = (q >> 1) & 3, j = q & 1;
+        const int v = q / (4 * NJ), i = (q / NJ) % 4, j = q % NJ;
         acc[u + v][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(afr[u & 1][i], bc[v][j],
                                                                  acc[u + v][i][j], 0, 0, 0);
       }
@@ -320,10 +329,10 @@ __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
   // epilogue: diagonal sums to binary64 (smallest scale first), scale by
   // 2^(e_i + f_j); 16 x 16 output layout
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int j = 0; j < NJ; ++j) {
+    const int64_t col = col0 + (wn * NJ + j) * 16 + lr;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int64_t col = col0 + wn * 32 + j * 16 + lr;
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = row0 + wm * 64 + i * 16 + lg * 4 + v;
@@ -341,7 +350,7 @@ __global__ __launch_bounds__(256) void ozaki_gemm_kernel(OzArgs g) {
           }
         }
       }
-    }
+  }
 }
 
 unsigned blocks_for(int64_t threads) {
@@ -354,7 +363,8 @@ hipError_t launch_oz(const OzArgs& g, hipStream_t s) {
   const int64_t items = g.tiles_m * g.tiles_n * g.splits;
   if (items <= 0) return hipSuccess;
   if (items > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(ozaki_gemm_kernel<S>, dim3((unsigned)items), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(ozaki_gemm_kernel<S>, dim3((unsigned)items), dim3(oz_waves<S>() * 64), 0, s,
+                     g);
   return hipGetLastError();
 }
 

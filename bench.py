@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--shapes", default="square,large_k,flat")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark step: FP64 shapes across the planner's "
+                         "regimes and the three tile sizes of one shape (one JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run one plain copy kernel (out = in * 1.0 over float64) "
                          "moving BYTES each way, to calibrate memory counters")
@@ -98,6 +101,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.sweep:
+        print(json.dumps({"sweep": run_sweep(torch, cm, synth, dev, stream, args.reps)}),
+              flush=True)
+        return
     wanted = args.shapes.split(",")
     shapes = [s for s in SHAPES if s[0] in wanted]
 
@@ -345,6 +352,56 @@ def run_variants(torch, cm, synth, dev, stream, keep, reps=20):
         "policy_candidates_ms": [round(x, 3) for x in pol_ms], "persistent_launches": groups,
         "work_items": items}
     keep.append(("batched", mats, dims, None, None, synth.UNIFORM_F32, "f32"))
+    return out
+
+
+# Equal-work FP64 shapes (2 mnk = 2^41) from deep k to wide C: the planner
+# cuts k (regime 1, split-K) while mn / S is below the number of CUs and
+# parallelises i, j only (regime 0) above it; then large-M and flat.
+SWEEP_SHAPES = [(1024, 1024, 1 << 20), (2048, 2048, 1 << 18), (4096, 4096, 1 << 16),
+                (8192, 8192, 1 << 14), (16384, 16384, 1 << 12), (1 << 20, 1024, 1024),
+                (65536, 65536, 256)]
+# One shape under each FP64 tile: less fast memory per CU in use, more I/O.
+SWEEP_TILES = (8192, 8192, 8192)
+
+
+def run_sweep(torch, cm, synth, dev, stream, reps):
+    out = {"regimes": [], "tiles": []}
+
+    def one(m, n, k, plan, tag):
+        A = torch.empty((m, k), dtype=torch.float64, device=dev)
+        B = torch.empty((k, n), dtype=torch.float64, device=dev)
+        C = torch.empty((m, n), dtype=torch.float64, device=dev)
+        synth.fill_device(A, SEED, synth.STREAM_A, synth.UNIFORM_F64)
+        synth.fill_device(B, SEED, synth.STREAM_B, synth.UNIFORM_F64)
+        cm.ensure_workspace(plan.workspace_bytes)
+        ms, st = _time(torch, stream, lambda: cm.gemm(A, B, C, dtype="f64", plan=plan, stream=stream),
+                       reps, min(3, reps))
+        tf = 2.0 * m * n * k / (ms * 1e-3) / 1e12
+        log(f"sweep {tag} {m}x{n}x{k}: {ms:.3f} ms {tf:.2f} TFLOP/s")
+        row = {"m": m, "n": n, "k": k, "tile": f"{plan.tile_m}x{plan.tile_n}", "p_k": plan.p_k,
+               "group_m": plan.group_m, "regime": plan.regime, "p1": round(plan.p1, 2),
+               "items": plan.items, "waves": plan.waves, "ms": ms, "ms_ci95": st["ci95"],
+               "tflops": round(tf, 3), "frac_peak": round(tf / PEAK_F64, 4),
+               "predicted_ms": round(plan.predicted_ms, 3),
+               "q_cu_words": plan.q_cu_words, "thm1_words": plan.thm1_words,
+               "q_cu_over_thm1": round(plan.q_cu_words / plan.thm1_words, 4),
+               "q_ea_bytes": plan.q_ea_bytes}
+        del A, B, C
+        torch.cuda.empty_cache()
+        return row
+
+    for (m, n, k) in SWEEP_SHAPES:
+        rc, plan = cm.cosma_plan_query(m, n, k, cm.COSMA_F64)
+        cm.check(rc, "plan")
+        out["regimes"].append(one(m, n, k, plan, "regime"))
+    m, n, k = SWEEP_TILES
+    for t in range(3):
+        rc, plan = cm.cosma_plan_make(m, n, k, cm.COSMA_F64, t, 1)
+        cm.check(rc, "plan")
+        row = one(m, n, k, plan, f"tile {t}")
+        row["tile_words_per_cu"] = plan.tile_m * plan.tile_n * plan.wg_per_cu
+        out["tiles"].append(row)
     return out
 
 

@@ -220,7 +220,8 @@ __device__ __forceinline__ void f64_tile(const GemmArgs& g, const ItemCoord& ic,
 }
 
 template <int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(WM* WN * 64) void gemm_f64_kernel(GemmArgs g) {
+__global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f64_kernel(
+    GemmArgs g) {
   using TL = F64Tile<BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) double As[2][TL::A_STAGE];
   __shared__ __attribute__((aligned(16))) double Bs[2][TL::B_STAGE];

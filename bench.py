@@ -293,7 +293,7 @@ def run_variants(torch, cm, synth, dev, stream, keep, reps=20):
     synth.fill_device(A, SEED, synth.STREAM_A, synth.WIDE_F64)
     synth.fill_device(B, SEED, synth.STREAM_B, synth.WIDE_F64)
     res = {}
-    for dt in ("f64", "ozaki"):
+    for dt in ("f64", "ozaki", "ozaki2"):
         C = torch.empty((m, n), dtype=torch.float64, device=dev)
         rc, plan = cm.cosma_plan_query(m, n, k, dt)
         cm.ensure_workspace(plan.workspace_bytes)
@@ -311,6 +311,16 @@ def run_variants(torch, cm, synth, dev, stream, keep, reps=20):
         "ozaki_tflops": round(res["ozaki"][1], 2),
         "ozaki_frac_int8_peak": round(res["ozaki"][1] * s_ * (s_ + 1) / 2 / PEAK_I8, 4),
         "speedup_vs_f64": round(res["f64"][0] / res["ozaki"][0], 3)}
+    nm = res["ozaki2"][2].slices
+    out["ozaki2_vs_f64"] = {
+        "shape": "8192^3, sign*U[1,2)*2^e, e in [-20,20]", "moduli": nm,
+        "beta": cm.cosma_ozaki2_params(k, nm)[1], "int8_products": nm,
+        "f64_ms": round(res["f64"][0], 3),
+        "ozaki2_ms": round(res["ozaki2"][0], 3), "ozaki2_ms_ci95": res["ozaki2"][3],
+        "ozaki2_tflops": round(res["ozaki2"][1], 2),
+        "ozaki2_frac_int8_peak": round(res["ozaki2"][1] * nm / PEAK_I8, 4),
+        "speedup_vs_f64": round(res["f64"][0] / res["ozaki2"][0], 3),
+        "speedup_vs_ozaki": round(res["ozaki"][0] / res["ozaki2"][0], 3)}
     del A, B
 
     dims = [tuple(int(x) for x in d) for d in synth.batch_dims(512, seed=5)]

@@ -54,9 +54,15 @@ typedef enum {
   COSMA_F32_BF16X3 = 2,   /* binary32 operands and result; each operand split
                              into bf16 hi + lo, three bf16 MFMA products,
                              fp32 accumulation */
-  COSMA_F64_OZAKI_I8 = 3  /* binary64 operands and result; operands split into
+  COSMA_F64_OZAKI_I8 = 3, /* binary64 operands and result; operands split into
                              int8 digit slices, exact int32 MFMA products,
                              binary64 summation */
+  COSMA_F64_OZAKI2_I8 = 4 /* binary64 operands and result; operands scaled to
+                             integers and reduced modulo N pairwise coprime
+                             moduli <= 256 (int8 residues), one exact int8
+                             MFMA product per modulus, result recovered by
+                             the Chinese remainder theorem (Ozaki, Uchino &
+                             Imamura, "Ozaki Scheme II", 2025) */
 } cosma_dtype;
 
 typedef enum {
@@ -92,7 +98,9 @@ typedef struct {
   int32_t group_m;            /* raster group height (tile rows per group) */
   int32_t wg_per_cu;          /* resident work items per CU */
   int32_t regime;             /* 0: ij-parallel (p <= p1), 1: k is cut (p > p1) */
-  int32_t slices;             /* Ozaki digit slices per operand (0 otherwise) */
+  int32_t slices;             /* COSMA_F64_OZAKI_I8: digit slices per operand;
+                                 COSMA_F64_OZAKI2_I8: number of moduli N;
+                                 0 otherwise */
   int64_t k_split;            /* reduction length per split (multiple of tile_k) */
   int64_t items;              /* p_m * p_n * p_k */
   int64_t waves;              /* ceil(items / resident slots) */
@@ -171,8 +179,21 @@ COSMA_API int cosma_plan_make(int64_t m, int64_t n, int64_t k, int dtype, int ti
                     cosma_plan_info* out);
 /* Ozaki plans: set the number of int8 digit slices per operand (1..8) and
    recompute the plan's workspace.  More slices cost s(s+1)/2 int8 products
-   and shrink the truncation error by 2^-7 per slice. */
+   and shrink the truncation error by 2^-7 per slice.
+   Modular (COSMA_F64_OZAKI2_I8) plans: set the number of moduli N (2..16)
+   and recompute the plan's work items and workspace.  Each modulus costs
+   one int8 product and adds about 8 bits to M; the operands keep beta bits
+   (see cosma_ozaki2_params), about half a bit less per doubling of k. */
 COSMA_API int cosma_plan_set_slices(cosma_plan_info* plan, int slices);
+/* Modular path parameters for reduction length k >= 1 and N moduli
+   (2..16): *beta receives the operand scale (rows of A and columns of B are
+   scaled so that their largest entry lies in [2^(beta-1), 2^beta) and
+   rounded to integers; every |sum_t A'_it B'_tj| <= k 2^(2 beta) <= M/4,
+   M = p_0 ... p_(N-1)), moduli[0..N) the moduli used (pairwise coprime,
+   taken greedily from 256 downwards).  Host only; returns
+   COSMA_ERR_INVALID_ARG when N is out of range or k is so long that
+   beta < 1. */
+COSMA_API int cosma_ozaki2_params(int64_t k, int nmod, int32_t* beta, int32_t* moduli);
 /* Number of kernel tiles for dtype, and the shape of tile `id`. */
 COSMA_API int cosma_tile_count(int dtype);
 COSMA_API int cosma_tile_shape(int dtype, int id, int32_t* tile_m, int32_t* tile_n, int32_t* tile_k);

@@ -21,7 +21,9 @@ COSMA_F64 = 0
 COSMA_F32 = 1
 COSMA_F32_BF16X3 = 2
 COSMA_F64_OZAKI_I8 = 3
-DTYPES = {"f64": COSMA_F64, "f32": COSMA_F32, "bf16x3": COSMA_F32_BF16X3, "ozaki": COSMA_F64_OZAKI_I8}
+COSMA_F64_OZAKI2_I8 = 4
+DTYPES = {"f64": COSMA_F64, "f32": COSMA_F32, "bf16x3": COSMA_F32_BF16X3, "ozaki": COSMA_F64_OZAKI_I8,
+          "ozaki2": COSMA_F64_OZAKI2_I8}
 
 COSMA_OK = 0
 COSMA_ERR_INVALID_ARG = -1
@@ -33,7 +35,7 @@ COSMA_ERR_NO_MEMORY = -5
 EXPORTED = [
     "cosma_gemm", "cosma_gemm_planned", "cosma_gemm_batched", "cosma_batch_create",
     "cosma_batch_run", "cosma_batch_destroy", "cosma_batch_info", "cosma_batch_tiles", "cosma_plan_query", "cosma_plan_query_facts",
-    "cosma_plan_make", "cosma_plan_set_slices", "cosma_tile_count", "cosma_tile_shape", "cosma_device_query",
+    "cosma_plan_make", "cosma_plan_set_slices", "cosma_ozaki2_params", "cosma_tile_count", "cosma_tile_shape", "cosma_device_query",
     "cosma_thm1_bound", "cosma_seq_schedule", "cosma_par_schedule", "cosma_fit_ranks",
     "cosma_io_count", "cosma_workspace_size", "cosma_set_workspace", "cosma_status_string",
     "cosma_version",
@@ -108,6 +110,8 @@ def lib():
                                                  ctypes.POINTER(cosma_device_facts), dbl, P]),
                 "cosma_plan_make": (i32, [i64, i64, i64, i32, i32, i32, P]),
                 "cosma_plan_set_slices": (i32, [P, i32]),
+                "cosma_ozaki2_params": (i32, [i64, i32, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32)]),
                 "cosma_tile_count": (i32, [i32]),
                 "cosma_tile_shape": (i32, [i32, i32, ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int32),
@@ -252,6 +256,14 @@ def cosma_plan_make(m, n, k, dtype, tile_id, p_k):
 
 def cosma_plan_set_slices(plan, slices) -> int:
     return lib().cosma_plan_set_slices(ctypes.byref(plan), int(slices))
+
+
+def cosma_ozaki2_params(k, nmod):
+    """Returns (status, beta, [moduli])."""
+    beta = ctypes.c_int32()
+    mods = (ctypes.c_int32 * max(1, int(nmod)))()
+    rc = lib().cosma_ozaki2_params(int(k), int(nmod), ctypes.byref(beta), mods)
+    return rc, beta.value, list(mods)[:max(0, int(nmod))]
 
 
 def cosma_tile_count(dtype) -> int:

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/cosma_mi355.h"
+#include "crt.hpp"
 #include "kernels.hpp"
 #include "ozaki.hpp"
 #include "planner.hpp"
@@ -216,6 +217,8 @@ int run_plan(const cosma_plan_info& plan, double alpha, const void* A, int64_t l
       return COSMA_ERR_WORKSPACE;
   }
   if (dtype == F64_OZAKI_I8) return run_ozaki(plan, alpha, A, lda, B, ldb, beta, C, ldc, ws, stream);
+  if (dtype == F64_OZAKI2_I8)
+    return run_ozaki2(plan, alpha, A, lda, B, ldb, beta, C, ldc, ws, stream);
   if (dtype == F32_BF16X3) return run_bf16x3(plan, alpha, A, lda, B, ldb, beta, C, ldc, ws, stream);
 
   GemmArgs g;
@@ -279,6 +282,9 @@ int check_plan(const cosma_plan_info* p) {
   if (ceil_div(p->k, p->k_split) != p->p_k) return COSMA_ERR_INVALID_ARG;
   if (p->group_m < 1) return COSMA_ERR_INVALID_ARG;
   if (p->dtype == F64_OZAKI_I8 && (p->slices < 1 || p->slices > 8)) return COSMA_ERR_INVALID_ARG;
+  if (p->dtype == F64_OZAKI2_I8 &&
+      (p->slices < CRT_MIN_MODULI || p->slices > CRT_MAX_MODULI || p->k_split > OZAKI2_MAX_K_ITEM))
+    return COSMA_ERR_INVALID_ARG;
   return COSMA_OK;
 }
 
@@ -348,9 +354,28 @@ int cosma_plan_make(int64_t m, int64_t n, int64_t k, int dtype, int tile_id, int
 }
 
 int cosma_plan_set_slices(cosma_plan_info* plan, int slices) {
-  if (!plan || plan->dtype != F64_OZAKI_I8 || slices < 1 || slices > 8) return COSMA_ERR_INVALID_ARG;
+  if (!plan) return COSMA_ERR_INVALID_ARG;
+  if (plan->dtype == F64_OZAKI_I8) {
+    if (slices < 1 || slices > 8) return COSMA_ERR_INVALID_ARG;
+  } else if (plan->dtype == F64_OZAKI2_I8) {
+    if (slices < CRT_MIN_MODULI || slices > CRT_MAX_MODULI) return COSMA_ERR_INVALID_ARG;
+    // one GEMM per modulus and split and tile
+    if (plan->p_m > 0 && plan->p_n > 0)
+      plan->items = (int64_t)plan->p_m * plan->p_n * plan->p_k * slices;
+  } else {
+    return COSMA_ERR_INVALID_ARG;
+  }
   plan->slices = slices;
   plan->workspace_bytes = workspace_bytes(*plan);
+  return COSMA_OK;
+}
+
+int cosma_ozaki2_params(int64_t k, int nmod, int32_t* beta, int32_t* moduli) {
+  if (!beta || !moduli) return COSMA_ERR_INVALID_ARG;
+  CrtParams cp;
+  if (!crt_params(k, nmod, &cp)) return COSMA_ERR_INVALID_ARG;
+  *beta = cp.beta;
+  for (int l = 0; l < nmod; ++l) moduli[l] = cp.p[l];
   return COSMA_OK;
 }
 

@@ -370,6 +370,19 @@ hipError_t launch_oz(const OzArgs& g, hipStream_t s) {
 
 }  // namespace
 
+hipError_t launch_ozaki_exponents(const double* A, int64_t m, int64_t k, int64_t lda,
+                                  const double* B, int64_t n, int64_t ldb, int* e, int* f,
+                                  hipStream_t stream) {
+  hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, stream, A, m, k,
+                     lda, e);
+  hipLaunchKernelGGL(fill_int_kernel, dim3(blocks_for(n) > 4096 ? 4096 : blocks_for(n)), dim3(256),
+                     0, stream, f, n, INT_MIN);
+  hipLaunchKernelGGL(col_exp_kernel, dim3(blocks_for(n), (unsigned)ceil_div(k, COL_CHUNK)),
+                     dim3(256), 0, stream, B, k, n, ldb, f);
+  hipLaunchKernelGGL(fix_exp_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, f, n);
+  return hipGetLastError();
+}
+
 int run_ozaki(const cosma_plan_info& plan, double alpha, const void* A, int64_t lda,
               const void* B, int64_t ldb, double beta, void* C, int64_t ldc, void* workspace,
               hipStream_t stream) {
@@ -391,13 +404,10 @@ int run_ozaki(const cosma_plan_info& plan, double alpha, const void* A, int64_t 
   int* f = e + m;
   hipError_t err;
 
-  hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)ceil_div(m, 4)), dim3(256), 0, stream,
-                     static_cast<const double*>(A), m, k, lda, e);
-  hipLaunchKernelGGL(fill_int_kernel, dim3(blocks_for(n) > 4096 ? 4096 : blocks_for(n)), dim3(256),
-                     0, stream, f, n, INT_MIN);
-  hipLaunchKernelGGL(col_exp_kernel, dim3(blocks_for(n), (unsigned)ceil_div(k, COL_CHUNK)),
-                     dim3(256), 0, stream, static_cast<const double*>(B), k, n, ldb, f);
-  hipLaunchKernelGGL(fix_exp_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, f, n);
+  if ((err = launch_ozaki_exponents(static_cast<const double*>(A), m, k, lda,
+                                    static_cast<const double*>(B), n, ldb, e, f, stream)) !=
+      hipSuccess)
+    return COSMA_ERR_HIP;
   hipLaunchKernelGGL(slice_a_kernel, dim3((unsigned)((a_rows / OZ_BM) * (kp / OZ_BK))), dim3(256), 0,
                      stream,
                      static_cast<const double*>(A), m, k, lda, e, s, a_planes, a_rows, kp);

@@ -1,4 +1,5 @@
-// FP64-accurate product from int8 digit slices (Ozaki scheme).
+// FP64-accurate products on the int8 matrix cores: digit slices (Ozaki
+// scheme) and modular residues (Ozaki scheme II).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,8 +8,20 @@
 
 namespace cosma {
 
+// Digit-slice path (dtype COSMA_F64_OZAKI_I8).
 int run_ozaki(const cosma_plan_info& plan, double alpha, const void* A, int64_t lda,
               const void* B, int64_t ldb, double beta, void* C, int64_t ldc, void* workspace,
               hipStream_t stream);
+
+// Modular path (dtype COSMA_F64_OZAKI2_I8).
+int run_ozaki2(const cosma_plan_info& plan, double alpha, const void* A, int64_t lda,
+               const void* B, int64_t ldb, double beta, void* C, int64_t ldc, void* workspace,
+               hipStream_t stream);
+
+// Row exponents of A (e[i]: max_t |A[i][t]| < 2^e[i]) and column exponents
+// of B (f[j]); all-zero rows and columns get 0.  Shared by both paths.
+hipError_t launch_ozaki_exponents(const double* A, int64_t m, int64_t k, int64_t lda,
+                                  const double* B, int64_t n, int64_t ldb, int* e, int* f,
+                                  hipStream_t stream);
 
 }  // namespace cosma

@@ -1,6 +1,8 @@
 // Host schedule planner.  See planner.hpp.
 #include "planner.hpp"
 
+#include "crt.hpp"
+
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -27,11 +29,16 @@ const TileDesc* tile_menu(int dtype, int* count) {
     case F32: *count = (int)(sizeof(kTilesF32) / sizeof(TileDesc)); return kTilesF32;
     case F32_BF16X3: *count = (int)(sizeof(kTilesBf16x3) / sizeof(TileDesc)); return kTilesBf16x3;
     case F64_OZAKI_I8: *count = (int)(sizeof(kTilesOzaki) / sizeof(TileDesc)); return kTilesOzaki;
+    case F64_OZAKI2_I8:
+      *count = (int)(sizeof(kTilesOzaki2) / sizeof(TileDesc));
+      return kTilesOzaki2;
     default: *count = 0; return nullptr;
   }
 }
 
-int word_bytes(int dtype) { return (dtype == F64 || dtype == F64_OZAKI_I8) ? 8 : 4; }
+int word_bytes(int dtype) {
+  return (dtype == F64 || dtype == F64_OZAKI_I8 || dtype == F64_OZAKI2_I8) ? 8 : 4;
+}
 int partial_bytes(int dtype) { return word_bytes(dtype); }
 
 int ozaki_slices() {
@@ -39,6 +46,15 @@ int ozaki_slices() {
     const char* e = std::getenv("COSMA_OZAKI_SLICES");
     int v = e ? std::atoi(e) : 7;
     return v < 1 ? 1 : (v > 8 ? 8 : v);
+  }();
+  return s;
+}
+
+int ozaki2_moduli() {
+  static int s = [] {
+    const char* e = std::getenv("COSMA_OZAKI2_MODULI");
+    int v = e ? std::atoi(e) : CRT_DEFAULT_MODULI;
+    return v < CRT_MIN_MODULI ? CRT_MIN_MODULI : (v > CRT_MAX_MODULI ? CRT_MAX_MODULI : v);
   }();
   return s;
 }
@@ -52,6 +68,8 @@ double useful_flops_per_clk_per_cu(int dtype, int slices) {
       const double pairs = slices * (slices + 1) / 2.0;
       return 8192.0 / (pairs > 0 ? pairs : 1.0);
     }
+    case F64_OZAKI2_I8:                   // one int8 product per modulus
+      return 8192.0 / (slices > 0 ? slices : 1);
     default: return 1.0;
   }
 }
@@ -212,6 +230,19 @@ double batch_item_cost(int64_t m, int64_t n, int64_t k, int dtype, int tile_id,
 
 size_t workspace_bytes(const cosma_plan_info& p) {
   if (p.m <= 0 || p.n <= 0 || p.k <= 0) return 0;
+  if (p.dtype == F64_OZAKI2_I8) {
+    // residue planes of A (rows padded to 256) and of B (columns padded to
+    // 128), k padded to 64; one residue byte per modulus, split and entry
+    // of the padded C; then per-row / per-column exponents
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t kp = (size_t)ceil_div(p.k, 64) * 64;
+    const size_t rows = (size_t)ceil_div(p.m, 256) * 256, cols = (size_t)ceil_div(p.n, 128) * 128;
+    const size_t nm = (size_t)(p.slices > 0 ? p.slices : 0);
+    const size_t planes = (size_t)crt_plane_bytes((int64_t)rows, 256, (int64_t)kp) +
+                          (size_t)crt_plane_bytes((int64_t)cols, 128, (int64_t)kp);
+    return up(nm * planes) + up((size_t)p.p_k * nm * rows * cols) +
+           up(((size_t)p.m + (size_t)p.n) * sizeof(int32_t));
+  }
   size_t ws = 0;
   if (p.p_k > 1) ws += (size_t)p.p_k * (size_t)p.m * (size_t)p.n * (size_t)partial_bytes(p.dtype);
   ws = (ws + 255) / 256 * 256;
@@ -269,12 +300,14 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
   out->n = n;
   out->k = k;
   out->dtype = dtype;
-  const int slices = dtype == F64_OZAKI_I8 ? ozaki_slices() : 0;
+  const bool oz2 = dtype == F64_OZAKI2_I8;
+  const int slices = dtype == F64_OZAKI_I8 ? ozaki_slices() : (oz2 ? ozaki2_moduli() : 0);
   out->slices = slices;
 
   // Fast memory of one CU in words of the stored operand (an Ozaki word is
-  // the s digit bytes of one element).
-  const double w = dtype == F64_OZAKI_I8 ? (double)slices : (double)word_bytes(dtype);
+  // the s digit bytes of one element, a modular word its residue bytes).
+  const double w =
+      (dtype == F64_OZAKI_I8 || oz2) ? (double)slices : (double)word_bytes(dtype);
   const double S = std::max(3.0, (double)(f.lds_bytes_per_cu + f.vgpr_bytes_per_cu) / w);
   out->S_words = S;
   const double P = (double)f.num_cus;
@@ -318,7 +351,10 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
   // with 256 / 512 / 1024 / 2048 rows).  Such pitches restrict the raster
   // groups to at most 512 A rows.
   if (a_pitch_bytes <= 0) a_pitch_bytes = k * (int64_t)word_bytes(dtype);
-  const bool pow2_pitch = dtype != F64_OZAKI_I8 && conflicting_pitch(a_pitch_bytes);
+  const bool pow2_pitch =
+      dtype != F64_OZAKI_I8 && !oz2 && conflicting_pitch(a_pitch_bytes);
+  // The modular path runs one GEMM per modulus in the same launch.
+  const int64_t per_tile = oz2 ? slices : 1;
   static const int kSplits[] = {1,  2,  3,  4,  5,  6,   8,   10,  12,  16,  20,
                                 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
   static const int kGroups[] = {1, 2, 4, 8, 16};
@@ -335,34 +371,49 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
       const int64_t splits = ceil_div(k, k_split);
       // Ozaki: a work item's int32 diagonal sums stay exact for <= 8192 k
       if (dtype == F64_OZAKI_I8 && k_split > 8192) continue;
+      // modular path: int32 sums of residue products stay exact
+      if (oz2 && k_split > OZAKI2_MAX_K_ITEM) continue;
       if (p_k <= 0 && splits != req) continue;  // duplicate of a smaller request
-      const int64_t items = tiles * splits;
+      const int64_t items = tiles * splits * per_tile;
       const int64_t slots = (int64_t)f.num_cus * T.wg_per_cu;
       const int64_t waves = ceil_div(items, slots);
-      const double item_flops = 2.0 * T.tm * T.tn * (double)k_split;
+      const double item_flops = 2.0 * T.tm * T.tn * (double)k_split / (double)per_tile;
       const double t_compute = (double)waves * item_flops / (per_cu_rate / T.wg_per_cu) / T.eff;
       double best_q = INFINITY;
       int best_g = 1;
       for (int g : kGroups) {
         if (g > 1 && g > ceil_div(m, T.tm)) break;
         if (g > 1 && pow2_pitch && g * T.tm > 512) break;
+        // modular path: per modulus a GEMM on one byte per element
         const double q = q_ea_bytes(m, n, k, k_split, splits, T.tm, T.tn, g,
-                                    (int64_t)cus_per_xcd * T.wg_per_cu, f.num_xcds, w);
+                                    (int64_t)cus_per_xcd * T.wg_per_cu, f.num_xcds,
+                                    oz2 ? 1.0 : w) *
+                         (double)per_tile;
         if (q < best_q * (1.0 - 1e-12)) {
           best_q = q;
           best_g = g;
         }
       }
-      // GEMM launch: operand panels + either C or the partial blocks.
-      const double gemm_bytes = best_q + (splits > 1 ? (double)splits * mn * pb : mn * wb);
-      // Reduce launch: reload the partials, store C.
-      const double reduce_bytes = splits > 1 ? (double)splits * mn * pb + mn * wb : 0.0;
-      // Ozaki prologue: read A and B once, write their digit planes.
+      // GEMM launch: operand panels + either C or the partial blocks (the
+      // modular path: one residue byte per modulus, split and entry).
+      const double out_bytes = oz2 ? (double)splits * slices * (double)(ceil_div(m, T.tm) * T.tm) *
+                                         (double)(ceil_div(n, T.tn) * T.tn)
+                                   : (splits > 1 ? (double)splits * mn * pb : mn * wb);
+      const double gemm_bytes = best_q + out_bytes;
+      // Reduce launch: reload the partials, store C (the modular path
+      // always reconstructs from its residues).
+      const double reduce_bytes =
+          oz2 ? out_bytes + mn * wb : (splits > 1 ? (double)splits * mn * pb + mn * wb : 0.0);
+      // Ozaki prologue: read A and B once, write their digit planes (the
+      // modular path reads them twice: exponents, then residues).
       const double pre_bytes =
-          dtype == F64_OZAKI_I8 ? ((double)m * k + (double)k * n) * (8.0 + slices) : 0.0;
+          dtype == F64_OZAKI_I8 ? ((double)m * k + (double)k * n) * (8.0 + slices)
+          : oz2                 ? ((double)m * k + (double)k * n) * (16.0 + slices)
+                                : 0.0;
       const double q_ea = gemm_bytes + reduce_bytes + pre_bytes;
       const double t_mem = gemm_bytes / hbm;
-      const double t_reduce = splits > 1 ? reduce_bytes / hbm + launch_overhead_s() : 0.0;
+      const double t_reduce =
+          (splits > 1 || oz2) ? reduce_bytes / hbm + launch_overhead_s() : 0.0;
       const double t_pre = pre_bytes > 0 ? pre_bytes / hbm + 2 * launch_overhead_s() : 0.0;
       Candidate c;
       c.tile_id = id;

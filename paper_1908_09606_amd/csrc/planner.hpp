@@ -25,6 +25,11 @@ double useful_flops_per_clk_per_cu(int dtype, int slices);
 
 // Number of int8 digit slices per operand used by the Ozaki path.
 int ozaki_slices();
+// Number of moduli used by the modular (Ozaki scheme II) path.
+int ozaki2_moduli();
+// Largest reduction length per work item of the modular path (int32 sums
+// of int8 residue products stay exact).
+constexpr int64_t OZAKI2_MAX_K_ITEM = 65536;
 
 // ---- the paper's schedule functions -----------------------------------
 double thm1_bound(double m, double n, double k, double S);                 // Theorem 1

@@ -13,7 +13,14 @@
 
 namespace cosma {
 
-enum Dtype : int { F64 = 0, F32 = 1, F32_BF16X3 = 2, F64_OZAKI_I8 = 3, NUM_DTYPES = 4 };
+enum Dtype : int {
+  F64 = 0,
+  F32 = 1,
+  F32_BF16X3 = 2,
+  F64_OZAKI_I8 = 3,
+  F64_OZAKI2_I8 = 4,
+  NUM_DTYPES = 5
+};
 
 // One compiled kernel variant: a tile_m x tile_n block of C per work item,
 // k streamed in rounds of tile_k (one LDS stage per round, double-buffered).
@@ -42,6 +49,9 @@ constexpr TileDesc kTilesBf16x3[] = {
 };
 constexpr TileDesc kTilesOzaki[] = {
     {128, 64, 64, 256, 1, 0.60},
+};
+constexpr TileDesc kTilesOzaki2[] = {
+    {256, 128, 64, 512, 2, 0.70},
 };
 
 COSMA_HD inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

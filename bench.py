@@ -51,10 +51,17 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """Hash of what decides the FP64 square launch's memory traffic: the
+    kernel source, its launch interface and the work-item raster.  The plan
+    (tile, group_m) is pinned separately by the record's kernel tag."""
     h = hashlib.sha256()
-    for name in ("gemm_f64.hip", "tiles.hpp", "kernels.hpp", "planner.cpp"):
-        with open(os.path.join(ROOT, "paper_1908_09606_amd", "csrc", name), "rb") as f:
+    csrc = os.path.join(ROOT, "paper_1908_09606_amd", "csrc")
+    for name in ("gemm_f64.hip", "kernels.hpp"):
+        with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
+    with open(os.path.join(csrc, "tiles.hpp"), "rb") as f:
+        tiles = f.read()
+    h.update(tiles[tiles.index(b"// Workgroups are handed to the XCDs"):])
     return h.hexdigest()[:16]
 
 

@@ -65,6 +65,11 @@ typedef enum {
                              Imamura, "Ozaki Scheme II", 2025) */
 } cosma_dtype;
 
+/* Storage order and operand transposition of cosma_gemm_ex (CBLAS
+   conventions). */
+typedef enum { COSMA_ROW_MAJOR = 0, COSMA_COL_MAJOR = 1 } cosma_layout;
+typedef enum { COSMA_NO_TRANS = 0, COSMA_TRANS = 1 } cosma_transpose;
+
 typedef enum {
   COSMA_OK = 0,
   COSMA_ERR_INVALID_ARG = -1, /* bad size, leading dimension, pointer, dtype or plan */
@@ -128,6 +133,27 @@ COSMA_API int cosma_gemm(int64_t m, int64_t n, int64_t k, double alpha, const vo
 COSMA_API int cosma_gemm_planned(const cosma_plan_info* plan, double alpha, const void* A, int64_t lda,
                        const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
                        void* stream);
+
+/* C = alpha*op(A)*op(B) + beta*C with CBLAS conventions, for callers whose
+   matrices are column-major (ScaLAPACK / Fortran style, the paper's own
+   library interface) or transposed.  op(A) is m x k, op(B) is k x n, C is
+   m x n.  Row-major: A is m x k (lda >= k) or, transposed, k x m (lda >= m);
+   B is k x n (ldb >= n) or n x k (ldb >= k); ldc >= n.  Column-major: A is
+   m x k (lda >= m) or k x m (lda >= k); B is k x n (ldb >= k) or n x k
+   (ldb >= n); ldc >= m.  (Leading dimensions are at least 1.)
+   A column-major product runs as the row-major product C^T = op(B)^T op(A)^T
+   on the same memory, with no copy.  A transposed operand (after that swap)
+   is first transposed into the workspace, after the part the plan itself
+   uses: register at least cosma_workspace_size_ex bytes.  Without transposed
+   operands this is cosma_gemm.  Errors, BLAS rules and asynchrony as for
+   cosma_gemm; COSMA_ERR_INVALID_ARG also for unknown layout or transpose
+   values. */
+COSMA_API int cosma_gemm_ex(int layout, int transa, int transb, int64_t m, int64_t n, int64_t k,
+                            double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+                            double beta, void* C, int64_t ldc, int dtype, void* stream);
+/* Workspace bytes cosma_gemm_ex needs for these arguments. */
+COSMA_API int cosma_workspace_size_ex(int layout, int transa, int transb, int64_t m, int64_t n,
+                                      int64_t k, int dtype, size_t* bytes);
 
 /* ---- batches of independent products (Algorithm 1's "for all p_i in
    parallel" over many small problems) ------------------------------------ */

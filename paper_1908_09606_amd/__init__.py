@@ -25,6 +25,11 @@ COSMA_F64_OZAKI2_I8 = 4
 DTYPES = {"f64": COSMA_F64, "f32": COSMA_F32, "bf16x3": COSMA_F32_BF16X3, "ozaki": COSMA_F64_OZAKI_I8,
           "ozaki2": COSMA_F64_OZAKI2_I8}
 
+COSMA_ROW_MAJOR = 0
+COSMA_COL_MAJOR = 1
+COSMA_NO_TRANS = 0
+COSMA_TRANS = 1
+
 COSMA_OK = 0
 COSMA_ERR_INVALID_ARG = -1
 COSMA_ERR_HIP = -2
@@ -33,7 +38,8 @@ COSMA_ERR_UNSUPPORTED = -4
 COSMA_ERR_NO_MEMORY = -5
 
 EXPORTED = [
-    "cosma_gemm", "cosma_gemm_planned", "cosma_gemm_batched", "cosma_batch_create",
+    "cosma_gemm", "cosma_gemm_planned", "cosma_gemm_ex", "cosma_workspace_size_ex",
+    "cosma_gemm_batched", "cosma_batch_create",
     "cosma_batch_run", "cosma_batch_destroy", "cosma_batch_info", "cosma_batch_tiles", "cosma_plan_query", "cosma_plan_query_facts",
     "cosma_plan_make", "cosma_plan_set_slices", "cosma_ozaki2_params", "cosma_tile_count", "cosma_tile_shape", "cosma_device_query",
     "cosma_thm1_bound", "cosma_seq_schedule", "cosma_par_schedule", "cosma_fit_ranks",
@@ -96,6 +102,10 @@ def lib():
             sig = {
                 "cosma_gemm": (i32, [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, vp]),
                 "cosma_gemm_planned": (i32, [P, dbl, vp, i64, vp, i64, dbl, vp, i64, vp]),
+                "cosma_gemm_ex": (i32, [i32, i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl,
+                                        vp, i64, i32, vp]),
+                "cosma_workspace_size_ex": (i32, [i32, i32, i32, i64, i64, i64, i32,
+                                                  ctypes.POINTER(ctypes.c_size_t)]),
                 "cosma_gemm_batched": (i32, [i64, pi64, pi64, pi64, pdbl, ppv, pi64, ppv, pi64,
                                              pdbl, ppv, pi64, i32, vp]),
                 "cosma_batch_create": (i32, [i64, pi64, pi64, pi64, pdbl, ppv, pi64, ppv, pi64,
@@ -190,6 +200,20 @@ def cosma_gemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, stream=None)
 def cosma_gemm_planned(plan, alpha, A, lda, B, ldb, beta, C, ldc, stream=None) -> int:
     return lib().cosma_gemm_planned(ctypes.byref(plan), float(alpha), _ptr(A), lda, _ptr(B), ldb,
                                     float(beta), _ptr(C), ldc, _stream(stream))
+
+
+def cosma_gemm_ex(layout, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype,
+                  stream=None) -> int:
+    return lib().cosma_gemm_ex(int(layout), int(transa), int(transb), m, n, k, float(alpha),
+                               _ptr(A), lda, _ptr(B), ldb, float(beta), _ptr(C), ldc,
+                               _dtype(dtype), _stream(stream))
+
+
+def cosma_workspace_size_ex(layout, transa, transb, m, n, k, dtype):
+    b = ctypes.c_size_t()
+    rc = lib().cosma_workspace_size_ex(int(layout), int(transa), int(transb), m, n, k,
+                                       _dtype(dtype), ctypes.byref(b))
+    return rc, b.value
 
 
 def cosma_gemm_batched(count, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype,

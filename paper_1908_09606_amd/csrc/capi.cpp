@@ -14,6 +14,7 @@
 #include "../../include/cosma_mi355.h"
 #include "crt.hpp"
 #include "kernels.hpp"
+#include "layout.hpp"
 #include "ozaki.hpp"
 #include "planner.hpp"
 #include "runtime.hpp"
@@ -288,6 +289,62 @@ int check_plan(const cosma_plan_info* p) {
   return COSMA_OK;
 }
 
+namespace {
+
+size_t up256(size_t x) { return (x + 255) / 256 * 256; }
+
+// CBLAS arguments brought to the row-major, no-transpose form of the
+// kernels: a column-major product C = op(A) op(B) is the row-major product
+// C^T = op(B)^T op(A)^T on the same memory, so layout swaps the operands,
+// their flags and m, n.  On return `ta` / `tb` say whether A / B (after the
+// swap) are stored transposed.  Leading dimensions are checked here.
+struct ExArgs {
+  int64_t m, n, k;
+  const void* A;
+  int64_t lda;
+  const void* B;
+  int64_t ldb;
+  bool ta, tb;
+};
+
+int normalise_ex(int layout, int transa, int transb, int64_t m, int64_t n, int64_t k,
+                 const void* A, int64_t lda, const void* B, int64_t ldb, int64_t ldc,
+                 ExArgs* out) {
+  if ((layout != COSMA_ROW_MAJOR && layout != COSMA_COL_MAJOR) ||
+      (transa != COSMA_NO_TRANS && transa != COSMA_TRANS) ||
+      (transb != COSMA_NO_TRANS && transb != COSMA_TRANS))
+    return COSMA_ERR_INVALID_ARG;
+  if (m < 0 || n < 0 || k < 0) return COSMA_ERR_INVALID_ARG;
+  ExArgs e;
+  if (layout == COSMA_ROW_MAJOR) {
+    e = ExArgs{m, n, k, A, lda, B, ldb, transa == COSMA_TRANS, transb == COSMA_TRANS};
+  } else {
+    e = ExArgs{n, m, k, B, ldb, A, lda, transb == COSMA_TRANS, transa == COSMA_TRANS};
+  }
+  // row-major: op(A) is m x k (stored k x m when transposed), op(B) k x n
+  const int64_t need_a = e.ta ? e.m : e.k, need_b = e.tb ? e.k : e.n;
+  if (e.lda < (need_a > 1 ? need_a : 1) || e.ldb < (need_b > 1 ? need_b : 1) ||
+      ldc < (e.n > 1 ? e.n : 1))
+    return COSMA_ERR_INVALID_ARG;
+  *out = e;
+  return COSMA_OK;
+}
+
+// Workspace of the product's plan followed by the transposed copies.
+size_t ex_workspace(const cosma_plan_info& plan, const ExArgs& e, int dtype) {
+  const size_t w = (size_t)word_bytes(dtype);
+  size_t ws = up256(workspace_bytes(plan));
+  if (e.ta) ws += up256((size_t)e.m * (size_t)e.k * w);
+  if (e.tb) ws += up256((size_t)e.k * (size_t)e.n * w);
+  return ws;
+}
+
+bool products_needed(const ExArgs& e, double alpha) {
+  return e.m > 0 && e.n > 0 && e.k > 0 && alpha != 0.0;
+}
+
+}  // namespace
+
 }  // namespace cosma
 
 using namespace cosma;
@@ -321,6 +378,83 @@ int cosma_gemm_planned(const cosma_plan_info* plan, double alpha, const void* A,
   device_facts(&st);
   if (st != COSMA_OK) return st;
   return run_plan(*plan, alpha, A, lda, B, ldb, beta, C, ldc, (hipStream_t)stream);
+}
+
+int cosma_gemm_ex(int layout, int transa, int transb, int64_t m, int64_t n, int64_t k,
+                  double alpha, const void* A, int64_t lda, const void* B, int64_t ldb,
+                  double beta, void* C, int64_t ldc, int dtype, void* stream) {
+  if (dtype < 0 || dtype >= NUM_DTYPES) return COSMA_ERR_INVALID_ARG;
+  ExArgs e;
+  int rc = normalise_ex(layout, transa, transb, m, n, k, A, lda, B, ldb, ldc, &e);
+  if (rc != COSMA_OK) return rc;
+  if (!e.ta && !e.tb)
+    return cosma_gemm(e.m, e.n, e.k, alpha, e.A, e.lda, e.B, e.ldb, beta, C, ldc, dtype, stream);
+  // operands as the row-major kernels see them: op(A) m x k, op(B) k x n
+  const int64_t lda_k = e.ta ? (e.k > 1 ? e.k : 1) : e.lda;
+  const int64_t ldb_k = e.tb ? (e.n > 1 ? e.n : 1) : e.ldb;
+  const size_t el = (size_t)word_bytes(dtype);
+  if (e.m == 0 || e.n == 0) return COSMA_OK;
+  if (!C || (uintptr_t)C % el) return COSMA_ERR_INVALID_ARG;
+  if (products_needed(e, alpha) &&
+      (!e.A || !e.B || (uintptr_t)e.A % el || (uintptr_t)e.B % el))
+    return COSMA_ERR_INVALID_ARG;
+  if (!products_needed(e, alpha))  // C = beta C, A and B not read
+    return cosma_gemm(e.m, e.n, e.k, alpha, e.A, lda_k, e.B, ldb_k, beta, C, ldc, dtype, stream);
+  int st = COSMA_OK;
+  device_facts(&st);
+  if (st != COSMA_OK) return st;
+  cosma_plan_info plan;
+  rc = plan_cached(e.m, e.n, e.k, dtype, &plan,
+                   e.ta ? e.k * (int64_t)el : e.lda * (int64_t)el);
+  if (rc != COSMA_OK) return rc;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  if (!workspace_for_current(&ws, &ws_bytes) || !ws || ws_bytes < ex_workspace(plan, e, dtype))
+    return COSMA_ERR_WORKSPACE;
+  char* tail = static_cast<char*>(ws) + up256(workspace_bytes(plan));
+  const void* Ak = e.A;
+  const void* Bk = e.B;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t err = hipSuccess;
+  if (e.ta) {  // A is stored k x m
+    if (el == 8)
+      err = launch_transpose_f64((const double*)e.A, e.k, e.m, e.lda, (double*)tail, s);
+    else
+      err = launch_transpose_f32((const float*)e.A, e.k, e.m, e.lda, (float*)tail, s);
+    Ak = tail;
+    tail += up256((size_t)e.m * (size_t)e.k * el);
+  }
+  if (err == hipSuccess && e.tb) {  // B is stored n x k
+    if (el == 8)
+      err = launch_transpose_f64((const double*)e.B, e.n, e.k, e.ldb, (double*)tail, s);
+    else
+      err = launch_transpose_f32((const float*)e.B, e.n, e.k, e.ldb, (float*)tail, s);
+    Bk = tail;
+  }
+  if (err != hipSuccess) return COSMA_ERR_HIP;
+  return run_plan(plan, alpha, Ak, lda_k, Bk, ldb_k, beta, C, ldc, s);
+}
+
+int cosma_workspace_size_ex(int layout, int transa, int transb, int64_t m, int64_t n, int64_t k,
+                            int dtype, size_t* bytes) {
+  if (!bytes || dtype < 0 || dtype >= NUM_DTYPES) return COSMA_ERR_INVALID_ARG;
+  ExArgs e;
+  // leading dimensions do not matter for the size: pass the smallest legal
+  const int64_t lda_min = layout == COSMA_ROW_MAJOR ? (transa == COSMA_TRANS ? m : k)
+                                                    : (transa == COSMA_TRANS ? k : m);
+  const int64_t ldb_min = layout == COSMA_ROW_MAJOR ? (transb == COSMA_TRANS ? k : n)
+                                                    : (transb == COSMA_TRANS ? n : k);
+  const int64_t ldc_min = layout == COSMA_ROW_MAJOR ? n : m;
+  const int rc = normalise_ex(layout, transa, transb, m, n, k, nullptr,
+                              lda_min > 1 ? lda_min : 1, nullptr, ldb_min > 1 ? ldb_min : 1,
+                              ldc_min > 1 ? ldc_min : 1, &e);
+  if (rc != COSMA_OK) return rc;
+  cosma_plan_info plan;
+  const int prc = cosma_plan_query(e.m, e.n, e.k, dtype, &plan);
+  if (prc != COSMA_OK) return prc;
+  *bytes = (e.ta || e.tb) && e.m > 0 && e.n > 0 && e.k > 0 ? ex_workspace(plan, e, dtype)
+                                                            : plan.workspace_bytes;
+  return COSMA_OK;
 }
 
 int cosma_plan_query(int64_t m, int64_t n, int64_t k, int dtype, cosma_plan_info* out) {

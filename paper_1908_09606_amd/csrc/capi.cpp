@@ -157,7 +157,7 @@ int run_bf16x3(const cosma_plan_info& plan, double alpha, const void* A, int64_t
   std::memset(&g, 0, sizeof(g));
   g.kp = ceil_div(k, 32) * 32;
   g.rows_p = ceil_div(m, 256) * 256;
-  g.cols_p = ceil_div(n, 128) * 128;
+  g.cols_p = ceil_div(n, 256) * 256;
   auto up = [](size_t x) { return (x + 255) / 256 * 256; };
   char* w = static_cast<char*>(ws);
   const size_t part = plan.p_k > 1 ? up((size_t)plan.p_k * m * n * sizeof(float)) : 0;

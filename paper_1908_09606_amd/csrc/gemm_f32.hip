@@ -305,8 +305,7 @@ __device__ __forceinline__ void split8(const float (&x)[8], us8& hi, us8& lo) {
 // order.  A plane: element (row, k) at
 //   ((k / 32) * rows_p + row) * 32 + x3_chunk(row, (k % 32) / 8) * 8 + k % 8
 // (rows_p = rows padded to 256, the tallest tile); B planes are stored
-// transposed, (col, k)
-// likewise with cols_p.  Padding rows, columns and k hold zeros, so a tile's
+// transposed, (col, k) likewise with cols_p (columns padded to 256).  Padding rows, columns and k hold zeros, so a tile's
 // round of any tile shape is one contiguous block, already in the swizzled
 // layout the GEMM's LDS uses, and the GEMM copies it with no bounds checks.
 constexpr int X3_K = 32;
@@ -635,6 +634,7 @@ hipError_t launch_gemm_bf16x3(int tile_id, const X3Args& g, hipStream_t s) {
     case 0: return launch_x3(gemm_bf16x3_kernel<128, 128, 32, 2, 2, 2>, 256, g, s);
     case 1: return launch_x3(gemm_bf16x3_kernel<64, 64, 32, 2, 2, 2>, 256, g, s);
     case 2: return launch_x3(gemm_bf16x3_kernel<256, 128, 32, 4, 2, 2>, 512, g, s);
+    case 3: return launch_x3(gemm_bf16x3_kernel<256, 256, 32, 4, 4, 2>, 1024, g, s);
     default: return hipErrorInvalidValue;
   }
 }

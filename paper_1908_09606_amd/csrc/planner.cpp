@@ -248,9 +248,9 @@ size_t workspace_bytes(const cosma_plan_info& p) {
   ws = (ws + 255) / 256 * 256;
   if (p.dtype == F32_BF16X3) {
     // bf16 hi and lo planes of A (rows padded to 256) and B (columns padded
-    // to 128, transposed), k padded to 32
+    // to 256, transposed), k padded to 32
     const size_t kp = (size_t)ceil_div(p.k, 32) * 32;
-    const size_t rows = (size_t)ceil_div(p.m, 256) * 256, cols = (size_t)ceil_div(p.n, 128) * 128;
+    const size_t rows = (size_t)ceil_div(p.m, 256) * 256, cols = (size_t)ceil_div(p.n, 256) * 256;
     ws += (2 * 2 * kp * (rows + cols) + 255) / 256 * 256;
   }
   if (p.dtype == F64_OZAKI_I8) {

@@ -46,6 +46,7 @@ constexpr TileDesc kTilesBf16x3[] = {
     {128, 128, 32, 256, 2, 0.48},
     {64, 64, 32, 256, 4, 0.35},
     {256, 128, 32, 512, 1, 0.45},
+    {256, 256, 32, 1024, 1, 0.57},
 };
 constexpr TileDesc kTilesOzaki[] = {
     {128, 64, 64, 256, 1, 0.60},

@@ -219,8 +219,10 @@ __device__ __forceinline__ void f64_tile(const GemmArgs& g, const ItemCoord& ic,
   }
 }
 
-template <int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(2))) void gemm_f64_kernel(
+// WPE: waves per SIMD the register allocation must allow (the tile menu's
+// blocks per CU times WM * WN / 4).
+template <int BM, int BN, int BK, int WM, int WN, int WPE>
+__global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void gemm_f64_kernel(
     GemmArgs g) {
   using TL = F64Tile<BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) double As[2][TL::A_STAGE];
@@ -306,12 +308,12 @@ unsigned elementwise_blocks(int64_t total) {
   return (unsigned)b;
 }
 
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int BK, int WM, int WN, int WPE>
 hipError_t launch_f64(const GemmArgs& g, hipStream_t s) {
   const int64_t items = g.tiles_m * g.tiles_n * g.splits;
   if (items <= 0) return hipSuccess;
   if (items > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN>), dim3((unsigned)items),
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, WPE>), dim3((unsigned)items),
                      dim3(WM * WN * 64), 0, s, g);
   return hipGetLastError();
 }
@@ -320,9 +322,9 @@ hipError_t launch_f64(const GemmArgs& g, hipStream_t s) {
 
 hipError_t launch_gemm_f64(int tile_id, const GemmArgs& g, hipStream_t s) {
   switch (tile_id) {
-    case 0: return launch_f64<128, 128, 16, 2, 2>(g, s);
-    case 1: return launch_f64<64, 64, 16, 2, 2>(g, s);
-    case 2: return launch_f64<256, 128, 16, 4, 2>(g, s);
+    case 0: return launch_f64<128, 128, 16, 4, 2, 4>(g, s);
+    case 1: return launch_f64<64, 64, 16, 2, 2, 4>(g, s);
+    case 2: return launch_f64<256, 128, 16, 4, 4, 4>(g, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -414,6 +414,14 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
       const double t_mem = gemm_bytes / hbm;
       const double t_reduce =
           (splits > 1 || oz2) ? reduce_bytes / hbm + launch_overhead_s() : 0.0;
+      // A tile that runs one block per CU exposes its epilogue: the C block
+      // (or partial) leaves at the CU's share of the memory bandwidth while
+      // nothing else computes on that CU.  With two or more blocks per CU
+      // the others' rounds hide it.
+      const double item_out_bytes =
+          (double)T.tm * T.tn * (oz2 ? (double)slices : (splits > 1 ? pb : wb));
+      const double t_epi =
+          T.wg_per_cu == 1 ? (double)waves * item_out_bytes / (hbm / (double)f.num_cus) : 0.0;
       const double t_pre = pre_bytes > 0 ? pre_bytes / hbm + 2 * launch_overhead_s() : 0.0;
       Candidate c;
       c.tile_id = id;
@@ -424,7 +432,7 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
       c.waves = waves;
       c.q_cu = io_count(m, n, k, T.tm, T.tn, T.tk, splits, false);
       c.q_ea = q_ea;
-      c.t = std::max(t_compute, t_mem) + t_reduce + t_pre + launch_overhead_s();
+      c.t = std::max(t_compute, t_mem) + t_epi + t_reduce + t_pre + launch_overhead_s();
       cands.push_back(c);
     }
   }

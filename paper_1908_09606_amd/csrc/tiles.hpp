@@ -33,9 +33,9 @@ struct TileDesc {
 
 // Menus, one per dtype; index = tile_id.  Order does not matter to the planner.
 constexpr TileDesc kTilesF64[] = {
-    {128, 128, 16, 256, 1, 0.90},
+    {128, 128, 16, 512, 2, 0.87},
     {64, 64, 16, 256, 4, 0.75},
-    {256, 128, 16, 512, 1, 0.92},
+    {256, 128, 16, 1024, 1, 0.855},
 };
 constexpr TileDesc kTilesF32[] = {
     {128, 128, 32, 256, 2, 0.80},
@@ -52,7 +52,7 @@ constexpr TileDesc kTilesOzaki[] = {
     {128, 64, 64, 256, 1, 0.60},
 };
 constexpr TileDesc kTilesOzaki2[] = {
-    {256, 128, 64, 512, 2, 0.70},
+    {256, 128, 64, 512, 2, 0.45},
 };
 
 COSMA_HD inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -210,8 +210,11 @@ __device__ __forceinline__ void f32_tile(const GemmArgs& g, const ItemCoord& ic,
   f32_epilogue<TL::MI, TL::NI, TL::WTM, TL::WTN>(g, ic, row0, col0, wm, wn, lr, lg, acc);
 }
 
-template <int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(WM* WN * 64) void gemm_f32_kernel(GemmArgs g) {
+// WPE: waves per SIMD the register allocation must allow (the tile menu's
+// blocks per CU times WM * WN / 4).
+template <int BM, int BN, int BK, int WM, int WN, int WPE>
+__global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void gemm_f32_kernel(
+    GemmArgs g) {
   using TL = F32Tile<BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) float As[2][TL::A_STAGE];
   __shared__ __attribute__((aligned(16))) float Bs[2][TL::B_STAGE];
@@ -562,9 +565,9 @@ hipError_t launch_items(K kernel, int threads, const GemmArgs& g, hipStream_t s)
 
 hipError_t launch_gemm_f32(int tile_id, const GemmArgs& g, hipStream_t s) {
   switch (tile_id) {
-    case 0: return launch_items(gemm_f32_kernel<128, 128, 32, 2, 2>, 256, g, s);
-    case 1: return launch_items(gemm_f32_kernel<64, 64, 32, 2, 2>, 256, g, s);
-    case 2: return launch_items(gemm_f32_kernel<256, 128, 32, 4, 2>, 512, g, s);
+    case 0: return launch_items(gemm_f32_kernel<128, 128, 32, 4, 2, 4>, 512, g, s);
+    case 1: return launch_items(gemm_f32_kernel<64, 64, 32, 2, 2, 4>, 256, g, s);
+    case 2: return launch_items(gemm_f32_kernel<256, 128, 32, 4, 4, 4>, 1024, g, s);
     default: return hipErrorInvalidValue;
   }
 }

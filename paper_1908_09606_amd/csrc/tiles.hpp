@@ -38,9 +38,9 @@ constexpr TileDesc kTilesF64[] = {
     {256, 128, 16, 1024, 1, 0.855},
 };
 constexpr TileDesc kTilesF32[] = {
-    {128, 128, 32, 256, 2, 0.80},
+    {128, 128, 32, 512, 2, 0.86},
     {64, 64, 32, 256, 4, 0.70},
-    {256, 128, 32, 512, 1, 0.85},
+    {256, 128, 32, 1024, 1, 0.865},
 };
 constexpr TileDesc kTilesBf16x3[] = {
     {128, 128, 32, 256, 2, 0.48},

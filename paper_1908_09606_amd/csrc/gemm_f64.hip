@@ -235,8 +235,9 @@ __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE
 // Persistent batched form: workgroups take (problem, tile) items from the
 // device counter until the list is exhausted; every item is computed as by
 // gemm_f64_kernel with one split.
-template <int BM, int BN, int BK, int WM, int WN>
-__global__ __launch_bounds__(WM* WN * 64) void gemm_f64_batched_kernel(BatchArgs b) {
+template <int BM, int BN, int BK, int WM, int WN, int WPE>
+__global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void gemm_f64_batched_kernel(
+    BatchArgs b) {
   using TL = F64Tile<BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) double As[2][TL::A_STAGE];
   __shared__ __attribute__((aligned(16))) double Bs[2][TL::B_STAGE];
@@ -349,18 +350,18 @@ int occupancy_of(K kernel, int threads) {
 
 hipError_t launch_batched_f64(int tile_id, const BatchArgs& b, int grid, hipStream_t s) {
   switch (tile_id) {
-    case 0: return launch_persistent(gemm_f64_batched_kernel<128, 128, 16, 2, 2>, 256, b, grid, s);
-    case 1: return launch_persistent(gemm_f64_batched_kernel<64, 64, 16, 2, 2>, 256, b, grid, s);
-    case 2: return launch_persistent(gemm_f64_batched_kernel<256, 128, 16, 4, 2>, 512, b, grid, s);
+    case 0: return launch_persistent(gemm_f64_batched_kernel<128, 128, 16, 4, 2, 4>, 512, b, grid, s);
+    case 1: return launch_persistent(gemm_f64_batched_kernel<64, 64, 16, 2, 2, 4>, 256, b, grid, s);
+    case 2: return launch_persistent(gemm_f64_batched_kernel<256, 128, 16, 4, 4, 4>, 1024, b, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 int batched_occupancy_f64(int tile_id) {
   switch (tile_id) {
-    case 0: return occupancy_of(gemm_f64_batched_kernel<128, 128, 16, 2, 2>, 256);
-    case 1: return occupancy_of(gemm_f64_batched_kernel<64, 64, 16, 2, 2>, 256);
-    case 2: return occupancy_of(gemm_f64_batched_kernel<256, 128, 16, 4, 2>, 512);
+    case 0: return occupancy_of(gemm_f64_batched_kernel<128, 128, 16, 4, 2, 4>, 512);
+    case 1: return occupancy_of(gemm_f64_batched_kernel<64, 64, 16, 2, 2, 4>, 256);
+    case 2: return occupancy_of(gemm_f64_batched_kernel<256, 128, 16, 4, 4, 4>, 1024);
     default: return 1;
   }
 }

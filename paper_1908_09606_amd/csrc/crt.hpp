@@ -13,7 +13,7 @@ namespace cosma {
 constexpr int CRT_MAX_MODULI = 16;
 constexpr int CRT_MIN_MODULI = 2;
 constexpr int CRT_DEFAULT_MODULI = 14;
-constexpr int CRT_MAX_BETA = 56;  // residues are taken in binary64 (see ozaki2.hip)
+constexpr int CRT_MAX_BETA = 50;  // residues are taken in binary64 (see ozaki2.hip)
 
 constexpr int CRT_LIMB_BITS = 30;
 constexpr int CRT_MAX_LIMBS = 5;  // M < 2^126 for 16 moduli

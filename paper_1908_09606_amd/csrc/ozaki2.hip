@@ -10,9 +10,9 @@
 //      B'_tj = rint(B_tj 2^(beta - f_j)), |A'|, |B'| <= 2^beta (exact in
 //      binary64).  beta is chosen on the host so that every
 //      |sum_t A'_it B'_tj| <= k 2^(2 beta) <= M / 4, M = prod p_l.
-//   3. Residues a_l = A' mod p_l, b_l = B' mod p_l in the symmetric range
-//      (int8, p_l <= 256), one plane per modulus, stored as MFMA operand
-//      fragments like the digit planes.
+//   3. Residues a_l = A' mod p_l, b_l = B' mod p_l, represented in
+//      [-128, 127] (int8, p_l <= 256), one plane per modulus, stored as MFMA
+//      operand fragments like the digit planes.
 //   4. Products: (a_l b_l)_ij exact in int32 (v_mfma_i32_16x16x64_i8, at
 //      most 65536 k per work item), reduced to y_l = (a_l b_l)_ij mod p_l
 //      and stored as one byte per modulus and k split, in the order the
@@ -63,15 +63,16 @@ __device__ __forceinline__ int frag_off(int rr, int g) {
   return (rr >> 4) * 1024 + (g * 16 + (rr & 15)) * 16;
 }
 
-// Symmetric residue of an integer-valued x (|x| <= 2^56) modulo p: q is
-// within one of rint(x / p) (relative error of x * pinv below 2^-51), the
-// fused x - p q is exact, and one correction lands in [-(p / 2), (p-1) / 2].
-__device__ __forceinline__ int sym_mod(double x, double p, double pinv, double lo, double hi) {
-  const double q = rint(x * pinv);
-  double r = fma(-p, q, x);
-  r = r > hi ? r - p : r;
-  r = r < lo ? r + p : r;
-  return (int)r;
+// A residue of an integer-valued x (|x| <= 2^50) modulo p that fits int8:
+// r = x - p rint(x * pinv) is exact (one fused rounding of a small integer),
+// and since x * pinv misses x / p by less than 2^-51 |x| / p, |x / p - q| <
+// 1/2 + 1/(2p), so |r| < p / 2 + 1/2 <= 128 for odd p <= 255.  For p = 256
+// the quotient is exact and r in [-128, 128]; its low byte is the
+// two's-complement residue either way.  Any representative in [-128, 127]
+// serves the int8 products (only r = x mod p matters), so no correction
+// step is needed.
+__device__ __forceinline__ unsigned residue_byte(double x, double p, double pinv) {
+  return (unsigned)(int)fma(-p, rint(x * pinv), x) & 0xffu;
 }
 
 // 16 integer-valued doubles -> one 16-byte group of residues per modulus.
@@ -79,14 +80,12 @@ __device__ __forceinline__ void residues16(const double (&x)[16], const CrtParam
                                            int8_t* __restrict__ out, int64_t plane_stride) {
   for (int l = 0; l < cp.nmod; ++l) {
     const double p = (double)cp.p[l], pinv = cp.pinv[l];
-    const double lo = -(double)(cp.p[l] / 2), hi = (double)((cp.p[l] - 1) / 2);
     unsigned w[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       unsigned v = 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        v |= ((unsigned)sym_mod(x[4 * q + b], p, pinv, lo, hi) & 0xffu) << (8 * b);
+      for (int b = 0; b < 4; ++b) v |= residue_byte(x[4 * q + b], p, pinv) << (8 * b);
       w[q] = v;
     }
     *reinterpret_cast<i4*>(out + l * plane_stride) = i4{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};

@@ -33,14 +33,15 @@ def test_moduli_and_beta(nmod, k):
     assert mods == greedy_coprime(nmod)
     assert all(2 <= p <= 256 for p in mods)
     assert all(gcd(a, b) == 1 for i, a in enumerate(mods) for b in mods[:i])
-    # symmetric residues fit int8
+    # residues within one half of the modulus fit int8
     assert all(-(p // 2) >= -128 and (p - 1) // 2 <= 127 for p in mods)
     # every |sum_t A'B'| <= k 2^(2 beta) stays within a quarter of M, so the
     # reconstruction's rint(X / M) cannot be off by one
-    assert 1 <= beta <= 56
+    assert 1 <= beta <= 50
     assert 4 * k * 4 ** beta <= M
     # and beta is not wasteful: at most 2 bits below the largest such value
-    assert beta == 56 or 4 * k * 4 ** (beta + 3) > M
+    # (or at the 50-bit cap under which residues need no correction step)
+    assert beta == 50 or 4 * k * 4 ** (beta + 3) > M
 
 
 def test_invalid_params():

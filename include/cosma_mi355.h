@@ -56,7 +56,11 @@ typedef enum {
                              fp32 accumulation */
   COSMA_F64_OZAKI_I8 = 3, /* binary64 operands and result; operands split into
                              int8 digit slices, exact int32 MFMA products,
-                             binary64 summation */
+                             binary64 summation.  Both Ozaki forms scale rows
+                             of A and columns of B: a row of A (column of B)
+                             holding a NaN or an infinity gives a NaN row
+                             (column) of C; the native dtypes follow IEEE
+                             arithmetic entry by entry */
   COSMA_F64_OZAKI2_I8 = 4 /* binary64 operands and result; operands scaled to
                              integers and reduced modulo N pairwise coprime
                              moduli <= 256 (int8 residues), one exact int8

@@ -45,19 +45,26 @@ constexpr int64_t COL_CHUNK = 256; // rows of B per block of the column-exponent
 
 // ---------------------------------------------------------------- exponents
 // One wave per row of A: e[i] = exponent of max_t |A[i][t]| (frexp form,
-// so max < 2^e); an all-zero row gets 0.
+// so max < 2^e); an all-zero row gets 0, a row with a NaN or an infinity
+// OZAKI_NONFINITE.
 __global__ __launch_bounds__(256) void row_exp_kernel(const double* __restrict__ A, int64_t m,
                                                       int64_t k, int64_t lda, int* __restrict__ e) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= m) return;
   double mx = 0.0;
-  for (int64_t t = lane; t < k; t += 64) mx = fmax(mx, fabs(A[row * lda + t]));
+  bool bad = false;
+  for (int64_t t = lane; t < k; t += 64) {
+    const double v = A[row * lda + t];
+    bad |= !isfinite(v);
+    mx = fmax(mx, fabs(v));
+  }
   for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  bad = __any(bad);
   if (lane == 0) {
     int ex = 0;
     if (mx > 0.0) frexp(mx, &ex);
-    e[row] = ex;
+    e[row] = bad ? OZAKI_NONFINITE : ex;
   }
 }
 
@@ -75,10 +82,15 @@ __global__ __launch_bounds__(256) void col_exp_kernel(const double* __restrict__
   const int64_t t0 = (int64_t)blockIdx.y * COL_CHUNK;
   const int64_t t1 = min64(k, t0 + COL_CHUNK);
   double mx = 0.0;
-  for (int64_t t = t0; t < t1; ++t) mx = fmax(mx, fabs(B[t * ldb + col]));
+  bool bad = false;
+  for (int64_t t = t0; t < t1; ++t) {
+    const double v = B[t * ldb + col];
+    bad |= !isfinite(v);
+    mx = fmax(mx, fabs(v));
+  }
   int ex = 0;
   if (mx > 0.0) frexp(mx, &ex);
-  atomicMax(f + col, ex);
+  atomicMax(f + col, bad ? OZAKI_NONFINITE : ex);  // the marker dominates
 }
 
 // Columns that are entirely zero end with INT_MIN from the fill: use 0.
@@ -140,7 +152,7 @@ __global__ __launch_bounds__(256) void slice_a_kernel(const double* __restrict__
     const int r = c / (OZ_BK / 2), kk = (c % (OZ_BK / 2)) * 2;
     const int64_t row = r0 + r;
     double x0 = 0.0, x1 = 0.0;
-    if (row < m) {
+    if (row < m && e[row] != OZAKI_NONFINITE) {
       const int sh = -e[row];
       if (k0 + kk < k) x0 = ldexp(A[row * lda + k0 + kk], sh);
       if (k0 + kk + 1 < k) x1 = ldexp(A[row * lda + k0 + kk + 1], sh);
@@ -171,7 +183,7 @@ __global__ __launch_bounds__(256) void slice_b_kernel(const double* __restrict__
   if (id >= cols * chunks) return;
   const int64_t kc = (id / cols) * 16, col = id - (id / cols) * cols;
   double x[16];
-  if (col < n) {
+  if (col < n && f[col] != OZAKI_NONFINITE) {
     const int sh = -f[col];
 #pragma unroll
     for (int i = 0; i < 16; ++i)
@@ -340,7 +352,10 @@ __global__ __launch_bounds__(oz_waves<S>() * 64) void ozaki_gemm_kernel(OzArgs g
           double x = 0.0;
 #pragma unroll
           for (int d = S - 1; d >= 0; --d) x += ldexp((double)acc[d][i][j][v], -7 * (d + 2));
-          const double r = ldexp(x, g.e[row] + g.f[col]);
+          const int er = g.e[row], fc = g.f[col];
+          const double r = (er == OZAKI_NONFINITE || fc == OZAKI_NONFINITE)
+                               ? __builtin_nan("")
+                               : ldexp(x, er + fc);
           if (g.splits == 1) {
             double* p = g.C + row * g.ldc + col;
             const double y = g.alpha * r;

@@ -19,7 +19,10 @@ int run_ozaki2(const cosma_plan_info& plan, double alpha, const void* A, int64_t
                hipStream_t stream);
 
 // Row exponents of A (e[i]: max_t |A[i][t]| < 2^e[i]) and column exponents
-// of B (f[j]); all-zero rows and columns get 0.  Shared by both paths.
+// of B (f[j]); all-zero rows and columns get 0, rows and columns holding a
+// NaN or an infinity get OZAKI_NONFINITE (their digits / residues are then
+// zero and their row / column of C is NaN).  Shared by both paths.
+constexpr int OZAKI_NONFINITE = 0x7fffffff;
 hipError_t launch_ozaki_exponents(const double* A, int64_t m, int64_t k, int64_t lda,
                                   const double* B, int64_t n, int64_t ldb, int* e, int* f,
                                   hipStream_t stream);

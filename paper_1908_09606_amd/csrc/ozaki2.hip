@@ -109,7 +109,8 @@ __global__ __launch_bounds__(256) void residue_a_kernel(const double* __restrict
     const int r = c >> 6, kk = c & 63;
     const int64_t row = rb * 64 + r, kt = R * O2_BK + kk;
     double x = 0.0;
-    if (row < m && kt < k) x = rint(ldexp(A[row * lda + kt], cp.beta - e[row]));
+    if (row < m && kt < k && e[row] != OZAKI_NONFINITE)
+      x = rint(ldexp(A[row * lda + kt], cp.beta - e[row]));
     tile[r][kk] = x;
   }
   __syncthreads();
@@ -141,7 +142,8 @@ __global__ __launch_bounds__(256) void residue_b_kernel(const double* __restrict
     const int kk = c >> 6, cc = c & 63;
     const int64_t col = cb * 64 + cc, kt = R * O2_BK + kk;
     double x = 0.0;
-    if (col < n && kt < k) x = rint(ldexp(B[kt * ldb + col], cp.beta - f[col]));
+    if (col < n && kt < k && f[col] != OZAKI_NONFINITE)
+      x = rint(ldexp(B[kt * ldb + col], cp.beta - f[col]));
     tile[kk][cc] = x;
   }
   __syncthreads();
@@ -399,7 +401,10 @@ __global__ __launch_bounds__(256) void crt_kernel(CrtArgs a) {
     double cpv = u[L - 1];
 #pragma unroll
     for (int i = L - 2; i >= 0; --i) cpv = fma(cpv, 0x1p30, u[i]);
-    const double r = ldexp(cpv, a.e[row] + fj - 2 * cp.beta);
+    const int er = a.e[row];
+    const double r = (er == OZAKI_NONFINITE || fj == OZAKI_NONFINITE)
+                         ? __builtin_nan("")
+                         : ldexp(cpv, er + fj - 2 * cp.beta);
     double* out = a.C + row * a.ldc + col;
     const double yv = a.alpha * r;
     *out = a.beta != 0.0 ? yv + a.beta * *out : yv;

@@ -160,3 +160,29 @@ def test_blas_quick_returns(gpu):
     C.copy_(C0)
     assert run_gemm(cm, m, n, 0, A, 1, B, n, C, n, 1.0, 2.0, dtype=OZ2) == 0
     assert torch.equal(C, 2.0 * C0)
+
+
+@pytest.mark.parametrize("dtype", ["ozaki", "ozaki2"])
+def test_nonfinite_rows_and_columns_give_nan(gpu, dtype):
+    """Both Ozaki forms scale whole rows of A and columns of B, so a NaN or an
+    infinity there makes that row / column of C NaN (with beta != 0 too);
+    every other entry stays the exact integer product."""
+    import torch
+    m, n, k = 140, 150, 300
+    _, A = device_matrix(m, k, 7, synth.STREAM_A, synth.INT_F64, 127)
+    _, B = device_matrix(k, n, 7, synth.STREAM_B, synth.INT_F64, 127)
+    Ah, Bh = A.cpu().numpy().astype(np.int64), B.cpu().numpy().astype(np.int64)
+    A[3, 5] = float("nan")
+    A[100, 0] = float("inf")
+    B[7, 2] = float("-inf")
+    B[299, 149] = float("nan")
+    C = torch.ones((m, n), dtype=torch.float64, device="cuda")
+    d = cm.DTYPES[dtype]
+    assert run_gemm(cm, m, n, k, A, k, B, n, C, n, 1.0, 2.0, dtype=d) == 0
+    Ch = C.cpu().numpy()
+    bad_r, bad_c = [3, 100], [2, 149]
+    assert np.isnan(Ch[bad_r, :]).all() and np.isnan(Ch[:, bad_c]).all()
+    keep_r = np.setdiff1d(np.arange(m), bad_r)
+    keep_c = np.setdiff1d(np.arange(n), bad_c)
+    exact = (Ah @ Bh).astype(np.float64) + 2.0
+    assert np.array_equal(Ch[np.ix_(keep_r, keep_c)], exact[np.ix_(keep_r, keep_c)])

@@ -97,8 +97,8 @@ def main():
                          "moving BYTES each way, to calibrate memory counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "path is not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library "
+              "runs each product on one GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -186,3 +186,44 @@ def test_nonfinite_rows_and_columns_give_nan(gpu, dtype):
     keep_c = np.setdiff1d(np.arange(n), bad_c)
     exact = (Ah @ Bh).astype(np.float64) + 2.0
     assert np.array_equal(Ch[np.ix_(keep_r, keep_c)], exact[np.ix_(keep_r, keep_c)])
+
+
+@pytest.mark.parametrize("nmod,k", [(14, 300), (9, 1000), (16, 64)])
+def test_equals_exact_scaled_integer_product(gpu, nmod, k):
+    """The modular path computes the scaled integer product exactly: with
+    e_i, f_j the exponents of the row / column maxima (max < 2^e) and beta
+    from cosma_ozaki2_params, A'_it = rint(A_it 2^(beta - e_i)) and
+    B'_tj = rint(B_tj 2^(beta - f_j)) are integers, C'_ij = sum_t A'_it B'_tj
+    is recovered exactly by the reconstruction, and C_ij is C'_ij 2^(e_i + f_j
+    - 2 beta) rounded to binary64 (the limb-by-limb conversion rounds up to
+    twice: within 2 ulps of the correctly rounded value).  Checked on
+    wide-exponent, non-integer data against big-integer arithmetic written
+    out here, far inside the 4k 2^-53 bound.""" 
+    import math
+    m, n = 37, 29
+    Ah = synth.gen(m, k, 31, synth.STREAM_A, synth.WIDE_F64)
+    Bh = synth.gen(k, n, 31, synth.STREAM_B, synth.WIDE_F64)
+    _, A = device_matrix(m, k, 31, synth.STREAM_A, synth.WIDE_F64)
+    _, B = device_matrix(k, n, 31, synth.STREAM_B, synth.WIDE_F64)
+    import torch
+    C = torch.full((m, n), float("nan"), dtype=torch.float64, device="cuda")
+    assert run_gemm(cm, m, n, k, A, k, B, n, C, n, plan=oz2_plan(m, n, k, nmod)) == 0
+    got = C.cpu().numpy()
+    rc, beta, _ = cm.cosma_ozaki2_params(k, nmod)
+    assert rc == 0
+    e = [math.frexp(float(np.max(np.abs(Ah[i]))))[1] for i in range(m)]
+    f = [math.frexp(float(np.max(np.abs(Bh[:, j]))))[1] for j in range(n)]
+    # scaling by a power of two is exact; rint of the scaled value is exact
+    Ai = [[int(np.rint(math.ldexp(float(Ah[i, t]), beta - e[i]))) for t in range(k)] for i in range(m)]
+    Bi = [[int(np.rint(math.ldexp(float(Bh[t, j]), beta - f[j]))) for t in range(k)] for j in range(n)]
+    worst = 0.0
+    for i in range(m):
+        for j in range(n):
+            exact = sum(a * b for a, b in zip(Ai[i], Bi[j]))
+            sh = e[i] + f[j] - 2 * beta
+            ref = math.ldexp(float(exact), sh) if abs(exact) < 2 ** 53 else \
+                float(exact * 2 ** sh) if sh >= 0 else exact / 2 ** (-sh)
+            ulps = abs(got[i, j] - ref) / math.ulp(ref) if ref != 0.0 else abs(got[i, j])
+            worst = max(worst, ulps)
+    log(f"  ozaki2 N={nmod} k={k} beta={beta}: worst {worst:.2f} ulp from the rounded exact product")
+    assert worst <= 2.0

@@ -198,7 +198,7 @@ def test_equals_exact_scaled_integer_product(gpu, nmod, k):
     - 2 beta) rounded to binary64 (the limb-by-limb conversion rounds up to
     twice: within 2 ulps of the correctly rounded value).  Checked on
     wide-exponent, non-integer data against big-integer arithmetic written
-    out here, far inside the 4k 2^-53 bound.""" 
+    out here, far inside the 4k 2^-53 bound."""
     import math
     m, n = 37, 29
     Ah = synth.gen(m, k, 31, synth.STREAM_A, synth.WIDE_F64)

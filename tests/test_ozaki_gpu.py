@@ -144,3 +144,51 @@ def test_blas_quick_returns(gpu):
     C.copy_(C0)
     assert run_gemm(cm, m, n, 0, A, 1, B, n, C, n, 1.0, 2.0, dtype=OZ) == 0
     assert torch.equal(C, 2.0 * C0)
+
+
+@pytest.mark.parametrize("slices", [3, 7])
+def test_equals_exact_truncated_digit_sum(gpu, slices):
+    """With one split the digit path computes, exactly up to its final
+    binary64 additions, 2^(e_i + f_j) sum_{u+v <= s+1} 2^-7(u+v) (A_u B_v)_ij:
+    digits from the recurrence d_u = trunc(2^7 r_(u-1)), r_u = 2^7 r_(u-1) -
+    d_u of A 2^-e (exact in binary64), integer products summed exactly here.
+    The kernel adds its s diagonal sums in binary64, so the result lies
+    within s ulps of the correctly rounded value."""
+    import math
+    m, n, k = 37, 29, 300
+    Ah = synth.gen(m, k, 33, synth.STREAM_A, synth.WIDE_F64)
+    Bh = synth.gen(k, n, 33, synth.STREAM_B, synth.WIDE_F64)
+    _, A = device_matrix(m, k, 33, synth.STREAM_A, synth.WIDE_F64)
+    _, B = device_matrix(k, n, 33, synth.STREAM_B, synth.WIDE_F64)
+    import torch
+    C = torch.full((m, n), float("nan"), dtype=torch.float64, device="cuda")
+    plan = oz_plan(m, n, k, slices)
+    assert plan.p_k == 1
+    assert run_gemm(cm, m, n, k, A, k, B, n, C, n, plan=plan) == 0
+    got = C.cpu().numpy()
+    e = np.array([math.frexp(float(np.max(np.abs(Ah[i]))))[1] for i in range(m)])
+    f = np.array([math.frexp(float(np.max(np.abs(Bh[:, j]))))[1] for j in range(n)])
+
+    def digits(X):  # rows of X already scaled into (-1, 1)
+        out = []
+        for _ in range(slices):
+            y = X * 128.0
+            d = np.trunc(y)
+            X = y - d
+            out.append(d.astype(np.int64))
+        return out
+
+    Ad = digits(np.ldexp(Ah, -e[:, None]))
+    Bd = digits(np.ldexp(Bh, -f[None, :]))
+    worst = 0.0
+    P = {(u, v): Ad[u] @ Bd[v] for u in range(slices) for v in range(slices) if u + v <= slices - 1}
+    for i in range(m):
+        for j in range(n):
+            # sum over pairs with weight 2^(7 (2s - (u+1) - (v+1))), exact integers
+            S = sum(int(p[i, j]) << (7 * (2 * slices - u - v - 2)) for (u, v), p in P.items())
+            sh = int(e[i] + f[j]) - 14 * slices
+            ref = S * 2 ** sh if sh >= 0 else S / 2 ** (-sh)
+            ulps = abs(got[i, j] - ref) / math.ulp(ref) if ref != 0.0 else abs(got[i, j])
+            worst = max(worst, ulps)
+    log(f"  ozaki s={slices}: worst {worst:.2f} ulp from the rounded exact truncated sum")
+    assert worst <= slices

@@ -264,7 +264,8 @@ def _time(torch, stream, fn, reps=20, warm=3):
 def run_variants(torch, cm, synth, dev, stream, keep, reps=20):
     """Precision and batching variants, each on its own workload:
     BF16x3 vs native FP32 (16384^3 and 4096^2 x 2^18, uniform FP32),
-    Ozaki INT8 slices vs native FP64 (8192^3, sign*U[1,2)*2^e, e in [-20,20]),
+    Ozaki INT8 slices, Ozaki II and Ozaki bf16 slices vs native FP64 (8192^3,
+    sign*U[1,2)*2^e, e in [-20,20]),
     512 uneven FP32 products: one graph launch vs 512 single launches.
     Results needed for the accuracy check are appended to `keep`."""
     out = {}
@@ -300,7 +301,7 @@ def run_variants(torch, cm, synth, dev, stream, keep, reps=20):
     synth.fill_device(A, SEED, synth.STREAM_A, synth.WIDE_F64)
     synth.fill_device(B, SEED, synth.STREAM_B, synth.WIDE_F64)
     res = {}
-    for dt in ("f64", "ozaki", "ozaki2"):
+    for dt in ("f64", "ozaki", "ozaki2", "ozaki_bf16"):
         C = torch.empty((m, n), dtype=torch.float64, device=dev)
         rc, plan = cm.cosma_plan_query(m, n, k, dt)
         cm.ensure_workspace(plan.workspace_bytes)
@@ -328,6 +329,17 @@ def run_variants(torch, cm, synth, dev, stream, keep, reps=20):
         "ozaki2_frac_int8_peak": round(res["ozaki2"][1] * nm / PEAK_I8, 4),
         "speedup_vs_f64": round(res["f64"][0] / res["ozaki2"][0], 3),
         "speedup_vs_ozaki": round(res["ozaki"][0] / res["ozaki2"][0], 3)}
+    sb = res["ozaki_bf16"][2].slices
+    out["ozaki_bf16_vs_f64"] = {
+        "shape": "8192^3, sign*U[1,2)*2^e, e in [-20,20]", "slices": sb,
+        "bf16_products": sb * (sb + 1) // 2,
+        "f64_ms": round(res["f64"][0], 3),
+        "ozaki_bf16_ms": round(res["ozaki_bf16"][0], 3),
+        "ozaki_bf16_ms_ci95": res["ozaki_bf16"][3],
+        "ozaki_bf16_tflops": round(res["ozaki_bf16"][1], 2),
+        "ozaki_bf16_frac_bf16_peak": round(res["ozaki_bf16"][1] * sb * (sb + 1) / 2 / PEAK_BF16, 4),
+        "speedup_vs_f64": round(res["f64"][0] / res["ozaki_bf16"][0], 3),
+        "speedup_vs_ozaki": round(res["ozaki"][0] / res["ozaki_bf16"][0], 3)}
     del A, B
 
     dims = [tuple(int(x) for x in d) for d in synth.batch_dims(512, seed=5)]

@@ -66,7 +66,13 @@ typedef enum {
                              moduli <= 256 (int8 residues), one exact int8
                              MFMA product per modulus, result recovered by
                              the Chinese remainder theorem (Ozaki, Uchino &
-                             Imamura, "Ozaki Scheme II", 2025) */
+                             Imamura, "Ozaki Scheme II", 2025) */,
+  COSMA_F64_OZAKI_BF16 = 5 /* binary64 operands and result; operands split
+                             into 8-bit digit slices held exactly in bf16,
+                             bf16 MFMA products with fp32 accumulation kept
+                             exact (every 32-long round is moved into a
+                             binary64 accumulator), binary64 summation;
+                             NaN rows / columns as COSMA_F64_OZAKI_I8 */
 } cosma_dtype;
 
 /* Storage order and operand transposition of cosma_gemm_ex (CBLAS
@@ -107,7 +113,8 @@ typedef struct {
   int32_t group_m;            /* raster group height (tile rows per group) */
   int32_t wg_per_cu;          /* resident work items per CU */
   int32_t regime;             /* 0: ij-parallel (p <= p1), 1: k is cut (p > p1) */
-  int32_t slices;             /* COSMA_F64_OZAKI_I8: digit slices per operand;
+  int32_t slices;             /* COSMA_F64_OZAKI_I8, COSMA_F64_OZAKI_BF16:
+                                 digit slices per operand;
                                  COSMA_F64_OZAKI2_I8: number of moduli N;
                                  0 otherwise */
   int64_t k_split;            /* reduction length per split (multiple of tile_k) */
@@ -207,9 +214,10 @@ COSMA_API int cosma_plan_query_facts(int64_t m, int64_t n, int64_t k, int dtype,
 /* Plan with a forced tile (menu index) and split factor p_k >= 1. */
 COSMA_API int cosma_plan_make(int64_t m, int64_t n, int64_t k, int dtype, int tile_id, int p_k,
                     cosma_plan_info* out);
-/* Ozaki plans: set the number of int8 digit slices per operand (1..8) and
-   recompute the plan's workspace.  More slices cost s(s+1)/2 int8 products
-   and shrink the truncation error by 2^-7 per slice.
+/* Ozaki plans: set the number of digit slices per operand (1..8) and
+   recompute the plan's workspace.  More slices cost s(s+1)/2 products and
+   shrink the truncation error by 2^-7 (COSMA_F64_OZAKI_I8) or 2^-8
+   (COSMA_F64_OZAKI_BF16) per slice.
    Modular (COSMA_F64_OZAKI2_I8) plans: set the number of moduli N (2..16)
    and recompute the plan's work items and workspace.  Each modulus costs
    one int8 product and adds about 8 bits to M; the operands keep beta bits

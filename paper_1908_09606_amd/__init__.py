@@ -22,8 +22,9 @@ COSMA_F32 = 1
 COSMA_F32_BF16X3 = 2
 COSMA_F64_OZAKI_I8 = 3
 COSMA_F64_OZAKI2_I8 = 4
+COSMA_F64_OZAKI_BF16 = 5
 DTYPES = {"f64": COSMA_F64, "f32": COSMA_F32, "bf16x3": COSMA_F32_BF16X3, "ozaki": COSMA_F64_OZAKI_I8,
-          "ozaki2": COSMA_F64_OZAKI2_I8}
+          "ozaki2": COSMA_F64_OZAKI2_I8, "ozaki_bf16": COSMA_F64_OZAKI_BF16}
 
 COSMA_ROW_MAJOR = 0
 COSMA_COL_MAJOR = 1

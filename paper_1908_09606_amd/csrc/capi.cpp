@@ -220,6 +220,8 @@ int run_plan(const cosma_plan_info& plan, double alpha, const void* A, int64_t l
   if (dtype == F64_OZAKI_I8) return run_ozaki(plan, alpha, A, lda, B, ldb, beta, C, ldc, ws, stream);
   if (dtype == F64_OZAKI2_I8)
     return run_ozaki2(plan, alpha, A, lda, B, ldb, beta, C, ldc, ws, stream);
+  if (dtype == F64_OZAKI_BF16)
+    return run_ozaki_bf16(plan, alpha, A, lda, B, ldb, beta, C, ldc, ws, stream);
   if (dtype == F32_BF16X3) return run_bf16x3(plan, alpha, A, lda, B, ldb, beta, C, ldc, ws, stream);
 
   GemmArgs g;
@@ -282,7 +284,8 @@ int check_plan(const cosma_plan_info* p) {
   if (p->p_k < 1 || p->k_split < T.tk || p->k_split % T.tk) return COSMA_ERR_INVALID_ARG;
   if (ceil_div(p->k, p->k_split) != p->p_k) return COSMA_ERR_INVALID_ARG;
   if (p->group_m < 1) return COSMA_ERR_INVALID_ARG;
-  if (p->dtype == F64_OZAKI_I8 && (p->slices < 1 || p->slices > 8)) return COSMA_ERR_INVALID_ARG;
+  if ((p->dtype == F64_OZAKI_I8 || p->dtype == F64_OZAKI_BF16) && (p->slices < 1 || p->slices > 8))
+    return COSMA_ERR_INVALID_ARG;
   if (p->dtype == F64_OZAKI2_I8 &&
       (p->slices < CRT_MIN_MODULI || p->slices > CRT_MAX_MODULI || p->k_split > OZAKI2_MAX_K_ITEM))
     return COSMA_ERR_INVALID_ARG;
@@ -489,7 +492,7 @@ int cosma_plan_make(int64_t m, int64_t n, int64_t k, int dtype, int tile_id, int
 
 int cosma_plan_set_slices(cosma_plan_info* plan, int slices) {
   if (!plan) return COSMA_ERR_INVALID_ARG;
-  if (plan->dtype == F64_OZAKI_I8) {
+  if (plan->dtype == F64_OZAKI_I8 || plan->dtype == F64_OZAKI_BF16) {
     if (slices < 1 || slices > 8) return COSMA_ERR_INVALID_ARG;
   } else if (plan->dtype == F64_OZAKI2_I8) {
     if (slices < CRT_MIN_MODULI || slices > CRT_MAX_MODULI) return COSMA_ERR_INVALID_ARG;

@@ -1,5 +1,5 @@
-// FP64-accurate products on the int8 matrix cores: digit slices (Ozaki
-// scheme) and modular residues (Ozaki scheme II).
+// FP64-accurate products on the int8 and bf16 matrix cores: digit slices
+// (Ozaki scheme, int8 or bf16 digits) and modular residues (Ozaki scheme II).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,6 +17,11 @@ int run_ozaki(const cosma_plan_info& plan, double alpha, const void* A, int64_t 
 int run_ozaki2(const cosma_plan_info& plan, double alpha, const void* A, int64_t lda,
                const void* B, int64_t ldb, double beta, void* C, int64_t ldc, void* workspace,
                hipStream_t stream);
+
+// Digit-slice path on the bf16 matrix cores (dtype COSMA_F64_OZAKI_BF16).
+int run_ozaki_bf16(const cosma_plan_info& plan, double alpha, const void* A, int64_t lda,
+                   const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
+                   void* workspace, hipStream_t stream);
 
 // Row exponents of A (e[i]: max_t |A[i][t]| < 2^e[i]) and column exponents
 // of B (f[j]); all-zero rows and columns get 0, rows and columns holding a

@@ -32,12 +32,18 @@ const TileDesc* tile_menu(int dtype, int* count) {
     case F64_OZAKI2_I8:
       *count = (int)(sizeof(kTilesOzaki2) / sizeof(TileDesc));
       return kTilesOzaki2;
+    case F64_OZAKI_BF16:
+      *count = (int)(sizeof(kTilesOzakiBf16) / sizeof(TileDesc));
+      return kTilesOzakiBf16;
     default: *count = 0; return nullptr;
   }
 }
 
 int word_bytes(int dtype) {
-  return (dtype == F64 || dtype == F64_OZAKI_I8 || dtype == F64_OZAKI2_I8) ? 8 : 4;
+  return (dtype == F64 || dtype == F64_OZAKI_I8 || dtype == F64_OZAKI2_I8 ||
+          dtype == F64_OZAKI_BF16)
+             ? 8
+             : 4;
 }
 int partial_bytes(int dtype) { return word_bytes(dtype); }
 
@@ -45,6 +51,15 @@ int ozaki_slices() {
   static int s = [] {
     const char* e = std::getenv("COSMA_OZAKI_SLICES");
     int v = e ? std::atoi(e) : 7;
+    return v < 1 ? 1 : (v > 8 ? 8 : v);
+  }();
+  return s;
+}
+
+int ozaki_bf16_slices() {
+  static int s = [] {
+    const char* e = std::getenv("COSMA_OZAKI_BF16_SLICES");
+    int v = e ? std::atoi(e) : 6;
     return v < 1 ? 1 : (v > 8 ? 8 : v);
   }();
   return s;
@@ -70,6 +85,10 @@ double useful_flops_per_clk_per_cu(int dtype, int slices) {
     }
     case F64_OZAKI2_I8:                   // one int8 product per modulus
       return 8192.0 / (slices > 0 ? slices : 1);
+    case F64_OZAKI_BF16: {                // s(s+1)/2 bf16 products per useful one
+      const double pairs = slices * (slices + 1) / 2.0;
+      return 4096.0 / (pairs > 0 ? pairs : 1.0);
+    }
     default: return 1.0;
   }
 }
@@ -253,6 +272,14 @@ size_t workspace_bytes(const cosma_plan_info& p) {
     const size_t rows = (size_t)ceil_div(p.m, 256) * 256, cols = (size_t)ceil_div(p.n, 256) * 256;
     ws += (2 * 2 * kp * (rows + cols) + 255) / 256 * 256;
   }
+  if (p.dtype == F64_OZAKI_BF16) {
+    // bf16 digit planes of A (rows padded to 128) and of B (columns padded
+    // to 64), k padded to 32, then per-row / per-column exponents
+    const size_t kp = (size_t)ceil_div(p.k, 32) * 32;
+    const size_t rows = (size_t)ceil_div(p.m, 128) * 128, cols = (size_t)ceil_div(p.n, 64) * 64;
+    ws += (2 * (size_t)p.slices * kp * (rows + cols) + 255) / 256 * 256;
+    ws += (((size_t)p.m + (size_t)p.n) * sizeof(int32_t) + 255) / 256 * 256;
+  }
   if (p.dtype == F64_OZAKI_I8) {
     // digit planes of A (rows padded to 128) and of B (columns padded to 64),
     // k padded to 64, then per-row / per-column exponents
@@ -301,13 +328,19 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
   out->k = k;
   out->dtype = dtype;
   const bool oz2 = dtype == F64_OZAKI2_I8;
-  const int slices = dtype == F64_OZAKI_I8 ? ozaki_slices() : (oz2 ? ozaki2_moduli() : 0);
+  const bool ozb = dtype == F64_OZAKI_BF16;
+  const int slices = dtype == F64_OZAKI_I8 ? ozaki_slices()
+                     : oz2                 ? ozaki2_moduli()
+                     : ozb                 ? ozaki_bf16_slices()
+                                           : 0;
   out->slices = slices;
 
   // Fast memory of one CU in words of the stored operand (an Ozaki word is
-  // the s digit bytes of one element, a modular word its residue bytes).
-  const double w =
-      (dtype == F64_OZAKI_I8 || oz2) ? (double)slices : (double)word_bytes(dtype);
+  // the s digit bytes of one element, two per digit on bf16, a modular word
+  // its residue bytes).
+  const double w = (dtype == F64_OZAKI_I8 || oz2) ? (double)slices
+                   : ozb                          ? 2.0 * slices
+                                                  : (double)word_bytes(dtype);
   const double S = std::max(3.0, (double)(f.lds_bytes_per_cu + f.vgpr_bytes_per_cu) / w);
   out->S_words = S;
   const double P = (double)f.num_cus;
@@ -352,7 +385,7 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
   // groups to at most 512 A rows.
   if (a_pitch_bytes <= 0) a_pitch_bytes = k * (int64_t)word_bytes(dtype);
   const bool pow2_pitch =
-      dtype != F64_OZAKI_I8 && !oz2 && conflicting_pitch(a_pitch_bytes);
+      dtype != F64_OZAKI_I8 && !oz2 && !ozb && conflicting_pitch(a_pitch_bytes);
   // The modular path runs one GEMM per modulus in the same launch.
   const int64_t per_tile = oz2 ? slices : 1;
   static const int kSplits[] = {1,  2,  3,  4,  5,  6,   8,   10,  12,  16,  20,
@@ -408,6 +441,7 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
       // modular path reads them twice: exponents, then residues).
       const double pre_bytes =
           dtype == F64_OZAKI_I8 ? ((double)m * k + (double)k * n) * (8.0 + slices)
+          : ozb                 ? ((double)m * k + (double)k * n) * (8.0 + 2.0 * slices)
           : oz2                 ? ((double)m * k + (double)k * n) * (16.0 + slices)
                                 : 0.0;
       const double q_ea = gemm_bytes + reduce_bytes + pre_bytes;

@@ -25,6 +25,8 @@ double useful_flops_per_clk_per_cu(int dtype, int slices);
 
 // Number of int8 digit slices per operand used by the Ozaki path.
 int ozaki_slices();
+// Number of bf16 digit slices per operand used by the bf16 Ozaki path.
+int ozaki_bf16_slices();
 // Number of moduli used by the modular (Ozaki scheme II) path.
 int ozaki2_moduli();
 // Largest reduction length per work item of the modular path (int32 sums

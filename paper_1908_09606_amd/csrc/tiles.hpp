@@ -19,7 +19,8 @@ enum Dtype : int {
   F32_BF16X3 = 2,
   F64_OZAKI_I8 = 3,
   F64_OZAKI2_I8 = 4,
-  NUM_DTYPES = 5
+  F64_OZAKI_BF16 = 5,
+  NUM_DTYPES = 6
 };
 
 // One compiled kernel variant: a tile_m x tile_n block of C per work item,
@@ -53,6 +54,9 @@ constexpr TileDesc kTilesOzaki[] = {
 };
 constexpr TileDesc kTilesOzaki2[] = {
     {256, 128, 64, 512, 2, 0.45},
+};
+constexpr TileDesc kTilesOzakiBf16[] = {
+    {128, 64, 32, 512, 1, 0.46},
 };
 
 COSMA_HD inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

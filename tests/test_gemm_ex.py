@@ -41,10 +41,12 @@ def test_unknown_flags_and_dtype():
 
 
 @pytest.mark.parametrize("dtype", [cm.COSMA_F64, cm.COSMA_F32, cm.COSMA_F32_BF16X3,
-                                   cm.COSMA_F64_OZAKI_I8, cm.COSMA_F64_OZAKI2_I8])
+                                   cm.COSMA_F64_OZAKI_I8, cm.COSMA_F64_OZAKI2_I8,
+                                   cm.COSMA_F64_OZAKI_BF16])
 def test_workspace_sizes(dtype):
     m, n, k = 300, 200, 1000
-    w = 8 if dtype in (cm.COSMA_F64, cm.COSMA_F64_OZAKI_I8, cm.COSMA_F64_OZAKI2_I8) else 4
+    w = 8 if dtype in (cm.COSMA_F64, cm.COSMA_F64_OZAKI_I8, cm.COSMA_F64_OZAKI2_I8,
+                       cm.COSMA_F64_OZAKI_BF16) else 4
     up = lambda x: (x + 255) // 256 * 256
     rc, base = cm.cosma_workspace_size(m, n, k, dtype)
     assert rc == 0

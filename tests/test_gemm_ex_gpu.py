@@ -49,7 +49,8 @@ SHAPES = [(1, 1, 1), (70, 45, 33), (257, 130, 300), (64, 200, 129)]
 
 
 @pytest.mark.parametrize("combo", COMBOS)
-@pytest.mark.parametrize("dtype", [cm.COSMA_F64, cm.COSMA_F32, cm.COSMA_F64_OZAKI2_I8])
+@pytest.mark.parametrize("dtype", [cm.COSMA_F64, cm.COSMA_F32, cm.COSMA_F64_OZAKI2_I8,
+                                   cm.COSMA_F64_OZAKI_BF16])
 def test_integer_exact(gpu, combo, dtype):
     import torch
     layout, ta, tb = combo

@@ -14,7 +14,8 @@ pytestmark = pytest.mark.gpu
 
 CASES = [("f64", (300, 257, 1000), 1), ("f64", (256, 128, 5000), 3), ("f32", (300, 257, 1000), 2),
          ("bf16x3", (513, 300, 700), 1), ("ozaki", (300, 257, 1000), 1),
-         ("ozaki2", (513, 300, 700), 1), ("ozaki2", (130, 140, 70000), 2)]
+         ("ozaki2", (513, 300, 700), 1), ("ozaki2", (130, 140, 70000), 2),
+         ("ozaki_bf16", (300, 257, 1000), 1), ("ozaki_bf16", (130, 140, 5000), 2)]
 
 
 @pytest.mark.parametrize("case", CASES)

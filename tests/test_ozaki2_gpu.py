@@ -162,9 +162,9 @@ def test_blas_quick_returns(gpu):
     assert torch.equal(C, 2.0 * C0)
 
 
-@pytest.mark.parametrize("dtype", ["ozaki", "ozaki2"])
+@pytest.mark.parametrize("dtype", ["ozaki", "ozaki2", "ozaki_bf16"])
 def test_nonfinite_rows_and_columns_give_nan(gpu, dtype):
-    """Both Ozaki forms scale whole rows of A and columns of B, so a NaN or an
+    """Every Ozaki form scales whole rows of A and columns of B, so a NaN or an
     infinity there makes that row / column of C NaN (with beta != 0 too);
     every other entry stays the exact integer product."""
     import torch

@@ -67,7 +67,7 @@ def test_io_count_equals_pebble_simulator():
                     assert cm.cosma_io_count(m, n, k, tm, tn, kc, pk, beta) == io
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16x3", "ozaki"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16x3", "ozaki", "ozaki_bf16"])
 @pytest.mark.parametrize("shape", [(512, 512, 512), (16384, 16384, 16384), (2048, 2048, 1 << 20),
                                    (32768, 32768, 256), (4096, 4096, 1 << 18), (8192, 8192, 8192),
                                    (1, 1, 1), (65, 3, 1000), (3000, 17, 5)])
@@ -84,14 +84,12 @@ def test_every_plan_respects_theorem1_and_is_consistent(dtype, shape):
     assert p.q_cu_words == cm.cosma_io_count(m, n, k, p.tile_m, p.tile_n, p.tile_k, p.p_k, False)
     assert p.regime == (1 if 256 > m * n / p.S_words else 0)
     # predicted memory traffic covers at least the compulsory traffic
-    w = 8 if dtype in ("f64",) else 4
-    if dtype == "ozaki":
-        w = 8
-    assert p.q_ea_bytes >= (m * k + k * n + m * n) * w * (1 - 1e-12) or dtype == "ozaki"
+    w = 8 if dtype in ("f64", "ozaki", "ozaki_bf16") else 4
+    assert p.q_ea_bytes >= (m * k + k * n + m * n) * w * (1 - 1e-12) or dtype.startswith("ozaki")
     rc, ws = cm.cosma_workspace_size(m, n, k, dtype)
     assert rc == 0 and ws == p.workspace_bytes
     if p.p_k > 1:
-        assert ws >= p.p_k * m * n * (8 if dtype in ("f64", "ozaki") else 4)
+        assert ws >= p.p_k * m * n * (8 if dtype in ("f64", "ozaki", "ozaki_bf16") else 4)
 
 
 def test_planner_regimes_on_paper_shapes():
@@ -151,3 +149,31 @@ def test_raster_groups_respect_conflicting_pitch():
         assert rc == 0 and (p.group_m == 1 or p.group_m * p.tile_m <= 512)
     rc, p = cm.cosma_plan_query(16000, 16000, 16000, "f64")        # pitch 128000 bytes
     assert rc == 0 and p.group_m * p.tile_m > 512
+
+
+def test_ozaki_bf16_plan_and_workspace():
+    """bf16 digit path: one 128 x 64 tile with 32-k rounds, 6 slices by
+    default (48 bits), 1..8 accepted; workspace = split partials, then 2 s
+    bytes per padded element of each operand's planes, then the exponents."""
+    up = lambda x: (x + 255) // 256 * 256
+    for (m, n, k, pk) in [(300, 200, 1000, 1), (129, 65, 33, 1), (200, 190, 3000, 3),
+                          (8192, 8192, 8192, 1)]:
+        rc, p = cm.cosma_plan_make(m, n, k, "ozaki_bf16", 0, pk)
+        assert rc == 0
+        assert (p.tile_m, p.tile_n, p.tile_k, p.slices) == (128, 64, 32, 6)
+        kp = -(-k // 32) * 32
+        rows, cols = -(-m // 128) * 128, -(-n // 64) * 64
+        part = up(pk * m * n * 8) if pk > 1 else 0
+        assert p.workspace_bytes == part + up(2 * 6 * kp * (rows + cols)) + up((m + n) * 4)
+        assert cm.cosma_plan_set_slices(p, 8) == 0
+        assert p.workspace_bytes == part + up(2 * 8 * kp * (rows + cols)) + up((m + n) * 4)
+        assert cm.cosma_plan_set_slices(p, 0) == cm.COSMA_ERR_INVALID_ARG
+        assert cm.cosma_plan_set_slices(p, 9) == cm.COSMA_ERR_INVALID_ARG
+    # a work item's reduction length is not limited (binary64 accumulation
+    # after every round): the square product runs without a split
+    rc, p = cm.cosma_plan_query(2048, 2048, 1 << 20, "ozaki_bf16")
+    assert rc == 0 and p.k_split > 65536
+    # the modelled rate is the bf16 rate over s(s+1)/2 products
+    rc, q = cm.cosma_plan_query(8192, 8192, 8192, "ozaki")
+    rc, b = cm.cosma_plan_query(8192, 8192, 8192, "ozaki_bf16")
+    assert b.predicted_ms > q.predicted_ms

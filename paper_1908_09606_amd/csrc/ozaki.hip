@@ -135,21 +135,26 @@ __device__ __forceinline__ int frag_offset(int rr, int g) {
   return (rr >> 4) * 1024 + (g * 16 + (rr & 15)) * 16;
 }
 
-// A: one workgroup per (row tile, k round): the 128 x 64 values are read in
-// 16-byte pieces, four rows of 256 contiguous bytes per wave instruction,
-// scaled and transposed through LDS; then each chunk of 16 consecutive k is
-// digitised and its 16 digit bytes per slice go to their fragment slot.
+// A: one workgroup per (row tile, k round, half of the round): the 128 x 32
+// values are read in 16-byte pieces, eight rows of 256 contiguous bytes per
+// wave instruction, scaled and transposed through LDS (34 KiB, so that
+// several workgroups share a CU); then each of the 256 chunks of 16
+// consecutive k is digitised by one thread and its 16 digit bytes per slice
+// go to their fragment slot (chunks 2 h, 2 h + 1 of the round: a wave writes
+// 512 contiguous bytes per slice).
+constexpr int SA_K = OZ_BK / 2;
 __global__ __launch_bounds__(256) void slice_a_kernel(const double* __restrict__ A, int64_t m,
                                                       int64_t k, int64_t lda,
                                                       const int* __restrict__ e, int s,
                                                       int8_t* __restrict__ planes, int64_t rows,
                                                       int64_t kp) {
-  __shared__ double tile[OZ_BM][OZ_BK + 1];
+  __shared__ double tile[OZ_BM][SA_K + 1];
   const int64_t rounds = kp / OZ_BK;
-  const int64_t blk = blockIdx.x;  // row_tile * rounds + round
-  const int64_t r0 = (blk / rounds) * OZ_BM, k0 = (blk % rounds) * OZ_BK;
-  for (int c = threadIdx.x; c < OZ_BM * OZ_BK / 2; c += 256) {
-    const int r = c / (OZ_BK / 2), kk = (c % (OZ_BK / 2)) * 2;
+  const int64_t blk = blockIdx.x >> 1;  // row_tile * rounds + round
+  const int half = blockIdx.x & 1;
+  const int64_t r0 = (blk / rounds) * OZ_BM, k0 = (blk % rounds) * OZ_BK + half * SA_K;
+  for (int c = threadIdx.x; c < OZ_BM * SA_K / 2; c += 256) {
+    const int r = c / (SA_K / 2), kk = (c % (SA_K / 2)) * 2;
     const int64_t row = r0 + r;
     double x0 = 0.0, x1 = 0.0;
     if (row < m && e[row] != OZAKI_NONFINITE) {
@@ -161,15 +166,13 @@ __global__ __launch_bounds__(256) void slice_a_kernel(const double* __restrict__
     tile[r][kk + 1] = x1;
   }
   __syncthreads();
-  // 512 chunks of 16 values (128 rows x 4): two per thread
-  for (int h = 0; h < 2; ++h) {
-    const int c = threadIdx.x + 256 * h;
-    const int r = c >> 2, kk = (c & 3) * 16;
-    double x[16];
+  // 256 chunks of 16 values (128 rows x 2): one per thread
+  const int c = threadIdx.x;
+  const int r = c >> 1, g = half * 2 + (c & 1);
+  double x[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) x[i] = tile[r][kk + i];
-    digits16(x, s, planes + blk * (OZ_BM * OZ_BK) + frag_offset(r, c & 3), rows * kp);
-  }
+  for (int i = 0; i < 16; ++i) x[i] = tile[r][(c & 1) * 16 + i];
+  digits16(x, s, planes + blk * (OZ_BM * OZ_BK) + frag_offset(r, g), rows * kp);
 }
 
 // B: thread per (column, 16-wide k chunk), columns fastest across the wave.
@@ -409,6 +412,10 @@ int run_ozaki(const cosma_plan_info& plan, double alpha, const void* A, int64_t 
   if (m > INT_MAX / 4 || n > INT_MAX / 4) return COSMA_ERR_UNSUPPORTED;
   const int64_t kp = ceil_div(k, OZ_BK) * OZ_BK;
   const int64_t a_rows = ceil_div(m, OZ_BM) * OZ_BM, b_cols = ceil_div(n, OZ_BN) * OZ_BN;
+  // the slice kernels' grids: two blocks per (row tile, round) for A, one
+  // thread per (column, 16 k) for B
+  if (2 * (a_rows / OZ_BM) * (kp / OZ_BK) > 0x7fffffffLL || b_cols * (kp / 16) / 256 > 0x7fffffffLL)
+    return COSMA_ERR_UNSUPPORTED;
   // workspace layout (matches workspace_bytes): partials | A planes, B planes | e, f
   auto up = [](size_t x) { return (x + 255) / 256 * 256; };
   char* w = static_cast<char*>(workspace);
@@ -423,8 +430,8 @@ int run_ozaki(const cosma_plan_info& plan, double alpha, const void* A, int64_t 
                                     static_cast<const double*>(B), n, ldb, e, f, stream)) !=
       hipSuccess)
     return COSMA_ERR_HIP;
-  hipLaunchKernelGGL(slice_a_kernel, dim3((unsigned)((a_rows / OZ_BM) * (kp / OZ_BK))), dim3(256), 0,
-                     stream,
+  hipLaunchKernelGGL(slice_a_kernel, dim3((unsigned)(2 * (a_rows / OZ_BM) * (kp / OZ_BK))),
+                     dim3(256), 0, stream,
                      static_cast<const double*>(A), m, k, lda, e, s, a_planes, a_rows, kp);
   hipLaunchKernelGGL(slice_b_kernel, dim3(blocks_for(b_cols * (kp / 16))), dim3(256), 0, stream,
                      static_cast<const double*>(B), k, n, ldb, f, s, b_planes, b_cols, kp);

@@ -56,7 +56,7 @@ typedef enum {
                              fp32 accumulation */
   COSMA_F64_OZAKI_I8 = 3, /* binary64 operands and result; operands split into
                              int8 digit slices, exact int32 MFMA products,
-                             binary64 summation.  Both Ozaki forms scale rows
+                             binary64 summation.  All Ozaki forms scale rows
                              of A and columns of B: a row of A (column of B)
                              holding a NaN or an infinity gives a NaN row
                              (column) of C; the native dtypes follow IEEE

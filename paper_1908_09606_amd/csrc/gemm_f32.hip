@@ -48,38 +48,96 @@ struct F32Tile {
   static_assert(2 * (A_STAGE + B_STAGE) * 4 <= 160 * 1024, "LDS budget");
 };
 
-template <class TL, int BM, int BN, int BK, bool CHECK>
-__device__ __forceinline__ void f32_load(const GemmArgs& g, int64_t row0, int64_t col0, int64_t k0,
-                                         int64_t kend, f4 (&ra)[TL::A_CHUNKS],
-                                         f4 (&rb)[TL::B_CHUNKS]) {
+// Operand loads of one round, per operand in one of three modes:
+// LOAD_VEC: 16-byte loads (base and row pitch 16-byte aligned, round in
+// bounds); LOAD_SCALAR: four 4-byte loads, no checks (in bounds, pitch not a
+// multiple of 16 bytes, e.g. an odd k or n); LOAD_CHECKED: element-wise with
+// zero fill (edge tiles and the last partial round).
+enum LoadMode { LOAD_VEC = 0, LOAD_SCALAR = 1, LOAD_CHECKED = 2 };
+
+template <class TL, int BM, int BN, int BK, int MODE>
+__device__ __forceinline__ void f32_load_a(const GemmArgs& g, int64_t row0, int64_t k0,
+                                           int64_t kend, f4 (&ra)[TL::A_CHUNKS]) {
   const float* __restrict__ A = static_cast<const float*>(g.A);
-  const float* __restrict__ B = static_cast<const float*>(g.B);
   const int t = threadIdx.x;
 #pragma unroll
   for (int i = 0; i < TL::A_CHUNKS; ++i) {
     const int c = t + TL::NT * i;
     const int r = c / (BK / 4), kk = (c % (BK / 4)) * 4;
     const int64_t gr = row0 + r, gk = k0 + kk;
-    if (!CHECK) {
-      ra[i] = *reinterpret_cast<const f4*>(A + gr * g.lda + gk);
+    const float* p = A + gr * g.lda + gk;
+    if (MODE == LOAD_VEC) {
+      ra[i] = *reinterpret_cast<const f4*>(p);
+    } else if (MODE == LOAD_SCALAR) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ra[i][e] = p[e];
     } else {
       const bool rin = gr < g.m;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) ra[i][e] = (rin && gk + e < kend) ? A[gr * g.lda + gk + e] : 0.0f;
+      for (int e = 0; e < 4; ++e) ra[i][e] = (rin && gk + e < kend) ? p[e] : 0.0f;
     }
   }
+}
+
+template <class TL, int BM, int BN, int BK, int MODE>
+__device__ __forceinline__ void f32_load_b(const GemmArgs& g, int64_t col0, int64_t k0,
+                                           int64_t kend, f4 (&rb)[TL::B_CHUNKS]) {
+  const float* __restrict__ B = static_cast<const float*>(g.B);
+  const int t = threadIdx.x;
 #pragma unroll
   for (int i = 0; i < TL::B_CHUNKS; ++i) {
     const int c = t + TL::NT * i;
     const int r = c / (BN / 4), nn = (c % (BN / 4)) * 4;
     const int64_t gk = k0 + r, gc = col0 + nn;
-    if (!CHECK) {
-      rb[i] = *reinterpret_cast<const f4*>(B + gk * g.ldb + gc);
+    const float* p = B + gk * g.ldb + gc;
+    if (MODE == LOAD_VEC) {
+      rb[i] = *reinterpret_cast<const f4*>(p);
+    } else if (MODE == LOAD_SCALAR) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rb[i][e] = p[e];
     } else {
       const bool kin = gk < kend;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) rb[i][e] = (kin && gc + e < g.n) ? B[gk * g.ldb + gc + e] : 0.0f;
+      for (int e = 0; e < 4; ++e) rb[i][e] = (kin && gc + e < g.n) ? p[e] : 0.0f;
     }
+  }
+}
+
+// One round's A and B panels.  FAST (a full tile with both operands 16-byte
+// aligned, decided once per work item): vector loads, element-wise only in
+// a partial last round; the common case keeps this short loop body.
+// Otherwise each operand takes its own mode; a_in / b_in say whether the
+// tile's rows of A / columns of B all lie inside the matrix.
+template <class TL, int BM, int BN, int BK, bool FAST>
+__device__ __forceinline__ void f32_load(const GemmArgs& g, int64_t row0, int64_t col0, int64_t k0,
+                                         int64_t kend, bool a_in, bool b_in,
+                                         f4 (&ra)[TL::A_CHUNKS], f4 (&rb)[TL::B_CHUNKS]) {
+  const bool k_in = k0 + BK <= kend;
+  if (FAST) {
+    if (k_in) {
+      f32_load_a<TL, BM, BN, BK, LOAD_VEC>(g, row0, k0, kend, ra);
+      f32_load_b<TL, BM, BN, BK, LOAD_VEC>(g, col0, k0, kend, rb);
+    } else {
+      f32_load_a<TL, BM, BN, BK, LOAD_CHECKED>(g, row0, k0, kend, ra);
+      f32_load_b<TL, BM, BN, BK, LOAD_CHECKED>(g, col0, k0, kend, rb);
+    }
+    return;
+  }
+  if (a_in && k_in) {
+    if (g.vec_a)
+      f32_load_a<TL, BM, BN, BK, LOAD_VEC>(g, row0, k0, kend, ra);
+    else
+      f32_load_a<TL, BM, BN, BK, LOAD_SCALAR>(g, row0, k0, kend, ra);
+  } else {
+    f32_load_a<TL, BM, BN, BK, LOAD_CHECKED>(g, row0, k0, kend, ra);
+  }
+  if (b_in && k_in) {
+    if (g.vec_b)
+      f32_load_b<TL, BM, BN, BK, LOAD_VEC>(g, col0, k0, kend, rb);
+    else
+      f32_load_b<TL, BM, BN, BK, LOAD_SCALAR>(g, col0, k0, kend, rb);
+  } else {
+    f32_load_b<TL, BM, BN, BK, LOAD_CHECKED>(g, col0, k0, kend, rb);
   }
 }
 
@@ -142,10 +200,10 @@ __device__ __forceinline__ void f32_epilogue(const GemmArgs& g, const ItemCoord&
 
 // One work item: the BM x BN block (ic.tile_row, ic.tile_col) over the
 // reduction range of split ic.split.  As / Bs: two LDS stages each.
-template <int BM, int BN, int BK, int WM, int WN>
-__device__ __forceinline__ void f32_tile(const GemmArgs& g, const ItemCoord& ic,
-                                         float (*As)[F32Tile<BM, BN, BK, WM, WN>::A_STAGE],
-                                         float (*Bs)[F32Tile<BM, BN, BK, WM, WN>::B_STAGE]) {
+template <int BM, int BN, int BK, int WM, int WN, bool FAST>
+__device__ __forceinline__ void f32_tile_body(const GemmArgs& g, const ItemCoord& ic,
+                                              float (*As)[F32Tile<BM, BN, BK, WM, WN>::A_STAGE],
+                                              float (*Bs)[F32Tile<BM, BN, BK, WM, WN>::B_STAGE]) {
   using TL = F32Tile<BM, BN, BK, WM, WN>;
   const int64_t row0 = ic.tile_row * BM, col0 = ic.tile_col * BN;
   const int64_t kbeg = ic.split * g.k_split;
@@ -154,7 +212,7 @@ __device__ __forceinline__ void f32_tile(const GemmArgs& g, const ItemCoord& ic,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int lr = lane & 15, lg = lane >> 4;
-  const bool full_mn = (row0 + BM <= g.m) && (col0 + BN <= g.n) && g.vec_a && g.vec_b;
+  const bool a_in = row0 + BM <= g.m, b_in = col0 + BN <= g.n;
 
   f4 acc[TL::MI][TL::NI];
 #pragma unroll
@@ -164,23 +222,16 @@ __device__ __forceinline__ void f32_tile(const GemmArgs& g, const ItemCoord& ic,
 
   f4 ra[TL::A_CHUNKS], rb[TL::B_CHUNKS];
   if (nk > 0) {
-    if (full_mn && kbeg + BK <= kend)
-      f32_load<TL, BM, BN, BK, false>(g, row0, col0, kbeg, kend, ra, rb);
-    else
-      f32_load<TL, BM, BN, BK, true>(g, row0, col0, kbeg, kend, ra, rb);
+    f32_load<TL, BM, BN, BK, FAST>(g, row0, col0, kbeg, kend, a_in, b_in, ra, rb);
     f32_store<TL, BM, BN, BK>(As[0], Bs[0], ra, rb);
   }
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int cur = (int)(kt & 1);
     const bool more = kt + 1 < nk;
-    if (more) {
-      const int64_t k0 = kbeg + (kt + 1) * BK;
-      if (full_mn && k0 + BK <= kend)
-        f32_load<TL, BM, BN, BK, false>(g, row0, col0, k0, kend, ra, rb);
-      else
-        f32_load<TL, BM, BN, BK, true>(g, row0, col0, k0, kend, ra, rb);
-    }
+    if (more)
+      f32_load<TL, BM, BN, BK, FAST>(g, row0, col0, kbeg + (kt + 1) * BK, kend, a_in, b_in, ra,
+                                     rb);
     const float* as = As[cur];
     const float* bs = Bs[cur];
 #pragma unroll
@@ -208,6 +259,19 @@ __device__ __forceinline__ void f32_tile(const GemmArgs& g, const ItemCoord& ic,
     __syncthreads();
   }
   f32_epilogue<TL::MI, TL::NI, TL::WTM, TL::WTN>(g, ic, row0, col0, wm, wn, lr, lg, acc);
+}
+
+// The two loop bodies are compiled apart and chosen once per work item.
+template <int BM, int BN, int BK, int WM, int WN>
+__device__ __forceinline__ void f32_tile(const GemmArgs& g, const ItemCoord& ic,
+                                         float (*As)[F32Tile<BM, BN, BK, WM, WN>::A_STAGE],
+                                         float (*Bs)[F32Tile<BM, BN, BK, WM, WN>::B_STAGE]) {
+  const bool fast = (ic.tile_row + 1) * BM <= g.m && (ic.tile_col + 1) * BN <= g.n && g.vec_a &&
+                    g.vec_b;
+  if (fast)
+    f32_tile_body<BM, BN, BK, WM, WN, true>(g, ic, As, Bs);
+  else
+    f32_tile_body<BM, BN, BK, WM, WN, false>(g, ic, As, Bs);
 }
 
 // WPE: waves per SIMD the register allocation must allow (the tile menu's

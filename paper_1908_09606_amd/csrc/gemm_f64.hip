@@ -49,14 +49,17 @@ struct F64Tile {
   static_assert(2 * (A_STAGE + B_STAGE) * 8 <= 160 * 1024, "LDS budget");
 };
 
-// Load one round's A and B panels into registers.  CHECK: bounds and
-// alignment are not guaranteed, load element by element with zero fill.
-template <class TL, int BM, int BN, int BK, bool CHECK>
-__device__ __forceinline__ void load_round(const GemmArgs& g, int64_t row0, int64_t col0,
-                                           int64_t k0, int64_t kend, d2 (&ra)[TL::A_CHUNKS],
-                                           d2 (&rb)[TL::B_CHUNKS]) {
+// Operand loads of one round, per operand in one of three modes:
+// LOAD_VEC: 16-byte loads (base and row pitch 16-byte aligned, round in
+// bounds); LOAD_SCALAR: two 8-byte loads, no checks (in bounds, pitch an odd
+// number of elements); LOAD_CHECKED: element-wise with zero fill (edge tiles
+// and the last partial round).
+enum LoadMode { LOAD_VEC = 0, LOAD_SCALAR = 1, LOAD_CHECKED = 2 };
+
+template <class TL, int BM, int BN, int BK, int MODE>
+__device__ __forceinline__ void load_a(const GemmArgs& g, int64_t row0, int64_t k0, int64_t kend,
+                                       d2 (&ra)[TL::A_CHUNKS]) {
   const double* __restrict__ A = static_cast<const double*>(g.A);
-  const double* __restrict__ B = static_cast<const double*>(g.B);
   const int t = threadIdx.x;
 #pragma unroll
   for (int i = 0; i < TL::A_CHUNKS; ++i) {
@@ -64,27 +67,80 @@ __device__ __forceinline__ void load_round(const GemmArgs& g, int64_t row0, int6
     const int r = c / (BK / 2);
     const int kk = (c % (BK / 2)) * 2;
     const int64_t gr = row0 + r, gk = k0 + kk;
-    if (!CHECK) {
-      ra[i] = *reinterpret_cast<const d2*>(A + gr * g.lda + gk);
+    const double* p = A + gr * g.lda + gk;
+    if (MODE == LOAD_VEC) {
+      ra[i] = *reinterpret_cast<const d2*>(p);
+    } else if (MODE == LOAD_SCALAR) {
+      ra[i].x = p[0];
+      ra[i].y = p[1];
     } else {
       const bool rin = gr < g.m;
-      ra[i].x = (rin && gk < kend) ? A[gr * g.lda + gk] : 0.0;
-      ra[i].y = (rin && gk + 1 < kend) ? A[gr * g.lda + gk + 1] : 0.0;
+      ra[i].x = (rin && gk < kend) ? p[0] : 0.0;
+      ra[i].y = (rin && gk + 1 < kend) ? p[1] : 0.0;
     }
   }
+}
+
+template <class TL, int BM, int BN, int BK, int MODE>
+__device__ __forceinline__ void load_b(const GemmArgs& g, int64_t col0, int64_t k0, int64_t kend,
+                                       d2 (&rb)[TL::B_CHUNKS]) {
+  const double* __restrict__ B = static_cast<const double*>(g.B);
+  const int t = threadIdx.x;
 #pragma unroll
   for (int i = 0; i < TL::B_CHUNKS; ++i) {
     const int c = t + TL::NT * i;
     const int r = c / (BN / 2);
     const int nn = (c % (BN / 2)) * 2;
     const int64_t gk = k0 + r, gc = col0 + nn;
-    if (!CHECK) {
-      rb[i] = *reinterpret_cast<const d2*>(B + gk * g.ldb + gc);
+    const double* p = B + gk * g.ldb + gc;
+    if (MODE == LOAD_VEC) {
+      rb[i] = *reinterpret_cast<const d2*>(p);
+    } else if (MODE == LOAD_SCALAR) {
+      rb[i].x = p[0];
+      rb[i].y = p[1];
     } else {
       const bool kin = gk < kend;
-      rb[i].x = (kin && gc < g.n) ? B[gk * g.ldb + gc] : 0.0;
-      rb[i].y = (kin && gc + 1 < g.n) ? B[gk * g.ldb + gc + 1] : 0.0;
+      rb[i].x = (kin && gc < g.n) ? p[0] : 0.0;
+      rb[i].y = (kin && gc + 1 < g.n) ? p[1] : 0.0;
     }
+  }
+}
+
+// One round's A and B panels into registers.  FAST (a full tile with both
+// operands 16-byte aligned, decided once per work item): vector loads,
+// element-wise only in a partial last round; the common case keeps this
+// short loop body.  Otherwise each operand takes its own mode; a_in / b_in
+// say whether the tile's rows of A / columns of B all lie inside the matrix.
+template <class TL, int BM, int BN, int BK, bool FAST>
+__device__ __forceinline__ void load_round(const GemmArgs& g, int64_t row0, int64_t col0,
+                                           int64_t k0, int64_t kend, bool a_in, bool b_in,
+                                           d2 (&ra)[TL::A_CHUNKS], d2 (&rb)[TL::B_CHUNKS]) {
+  const bool k_in = k0 + BK <= kend;
+  if (FAST) {
+    if (k_in) {
+      load_a<TL, BM, BN, BK, LOAD_VEC>(g, row0, k0, kend, ra);
+      load_b<TL, BM, BN, BK, LOAD_VEC>(g, col0, k0, kend, rb);
+    } else {
+      load_a<TL, BM, BN, BK, LOAD_CHECKED>(g, row0, k0, kend, ra);
+      load_b<TL, BM, BN, BK, LOAD_CHECKED>(g, col0, k0, kend, rb);
+    }
+    return;
+  }
+  if (a_in && k_in) {
+    if (g.vec_a)
+      load_a<TL, BM, BN, BK, LOAD_VEC>(g, row0, k0, kend, ra);
+    else
+      load_a<TL, BM, BN, BK, LOAD_SCALAR>(g, row0, k0, kend, ra);
+  } else {
+    load_a<TL, BM, BN, BK, LOAD_CHECKED>(g, row0, k0, kend, ra);
+  }
+  if (b_in && k_in) {
+    if (g.vec_b)
+      load_b<TL, BM, BN, BK, LOAD_VEC>(g, col0, k0, kend, rb);
+    else
+      load_b<TL, BM, BN, BK, LOAD_SCALAR>(g, col0, k0, kend, rb);
+  } else {
+    load_b<TL, BM, BN, BK, LOAD_CHECKED>(g, col0, k0, kend, rb);
   }
 }
 
@@ -111,10 +167,10 @@ __device__ __forceinline__ void store_round(double* __restrict__ As, double* __r
 
 // One work item: the BM x BN block (ic.tile_row, ic.tile_col) over the
 // reduction range of split ic.split.  As / Bs: two LDS stages each.
-template <int BM, int BN, int BK, int WM, int WN>
-__device__ __forceinline__ void f64_tile(const GemmArgs& g, const ItemCoord& ic,
-                                         double (*As)[F64Tile<BM, BN, BK, WM, WN>::A_STAGE],
-                                         double (*Bs)[F64Tile<BM, BN, BK, WM, WN>::B_STAGE]) {
+template <int BM, int BN, int BK, int WM, int WN, bool FAST>
+__device__ __forceinline__ void f64_tile_body(const GemmArgs& g, const ItemCoord& ic,
+                                              double (*As)[F64Tile<BM, BN, BK, WM, WN>::A_STAGE],
+                                              double (*Bs)[F64Tile<BM, BN, BK, WM, WN>::B_STAGE]) {
   using TL = F64Tile<BM, BN, BK, WM, WN>;
   const int64_t row0 = ic.tile_row * BM, col0 = ic.tile_col * BN;
   const int64_t kbeg = ic.split * g.k_split;
@@ -126,7 +182,7 @@ __device__ __forceinline__ void f64_tile(const GemmArgs& g, const ItemCoord& ic,
   const int wm = wave / WN, wn = wave % WN;
   const int lr = lane & 15, lg = lane >> 4;
 
-  const bool full_mn = (row0 + BM <= g.m) && (col0 + BN <= g.n) && g.vec_a && g.vec_b;
+  const bool a_in = row0 + BM <= g.m, b_in = col0 + BN <= g.n;
 
   d4 acc[TL::MI][TL::NI];
 #pragma unroll
@@ -136,10 +192,7 @@ __device__ __forceinline__ void f64_tile(const GemmArgs& g, const ItemCoord& ic,
 
   d2 ra[TL::A_CHUNKS], rb[TL::B_CHUNKS];
   if (nk > 0) {
-    if (full_mn && kbeg + BK <= kend)
-      load_round<TL, BM, BN, BK, false>(g, row0, col0, kbeg, kend, ra, rb);
-    else
-      load_round<TL, BM, BN, BK, true>(g, row0, col0, kbeg, kend, ra, rb);
+    load_round<TL, BM, BN, BK, FAST>(g, row0, col0, kbeg, kend, a_in, b_in, ra, rb);
     store_round<TL, BM, BN, BK>(As[0], Bs[0], ra, rb);
   }
   __syncthreads();
@@ -147,13 +200,9 @@ __device__ __forceinline__ void f64_tile(const GemmArgs& g, const ItemCoord& ic,
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int cur = (int)(kt & 1);
     const bool more = kt + 1 < nk;
-    if (more) {
-      const int64_t k0 = kbeg + (kt + 1) * BK;
-      if (full_mn && k0 + BK <= kend)
-        load_round<TL, BM, BN, BK, false>(g, row0, col0, k0, kend, ra, rb);
-      else
-        load_round<TL, BM, BN, BK, true>(g, row0, col0, k0, kend, ra, rb);
-    }
+    if (more)
+      load_round<TL, BM, BN, BK, FAST>(g, row0, col0, kbeg + (kt + 1) * BK, kend, a_in, b_in, ra,
+                                       rb);
     const double* __restrict__ as = As[cur];
     const double* __restrict__ bs = Bs[cur];
 #pragma unroll
@@ -217,6 +266,19 @@ __device__ __forceinline__ void f64_tile(const GemmArgs& g, const ItemCoord& ic,
         }
       }
   }
+}
+
+// The two loop bodies are compiled apart and chosen once per work item.
+template <int BM, int BN, int BK, int WM, int WN>
+__device__ __forceinline__ void f64_tile(const GemmArgs& g, const ItemCoord& ic,
+                                         double (*As)[F64Tile<BM, BN, BK, WM, WN>::A_STAGE],
+                                         double (*Bs)[F64Tile<BM, BN, BK, WM, WN>::B_STAGE]) {
+  const bool fast = (ic.tile_row + 1) * BM <= g.m && (ic.tile_col + 1) * BN <= g.n && g.vec_a &&
+                    g.vec_b;
+  if (fast)
+    f64_tile_body<BM, BN, BK, WM, WN, true>(g, ic, As, Bs);
+  else
+    f64_tile_body<BM, BN, BK, WM, WN, false>(g, ic, As, Bs);
 }
 
 // WPE: waves per SIMD the register allocation must allow (the tile menu's

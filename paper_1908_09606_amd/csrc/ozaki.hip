@@ -54,7 +54,8 @@ __global__ __launch_bounds__(256) void row_exp_kernel(const double* __restrict__
   if (row >= m) return;
   double mx = 0.0;
   bool bad = false;
-  for (int64_t t = lane; t < k; t += 64) {
+#pragma unroll 8
+  for (int64_t t = lane; t < k; t += 64) {  // unrolled: eight loads in flight per lane
     const double v = A[row * lda + t];
     bad |= !isfinite(v);
     mx = fmax(mx, fabs(v));
@@ -83,7 +84,8 @@ __global__ __launch_bounds__(256) void col_exp_kernel(const double* __restrict__
   const int64_t t1 = min64(k, t0 + COL_CHUNK);
   double mx = 0.0;
   bool bad = false;
-  for (int64_t t = t0; t < t1; ++t) {
+#pragma unroll 8
+  for (int64_t t = t0; t < t1; ++t) {  // unrolled: eight loads in flight per thread
     const double v = B[t * ldb + col];
     bad |= !isfinite(v);
     mx = fmax(mx, fabs(v));
@@ -156,11 +158,17 @@ __global__ __launch_bounds__(256) void slice_a_kernel(const double* __restrict__
   for (int c = threadIdx.x; c < OZ_BM * SA_K / 2; c += 256) {
     const int r = c / (SA_K / 2), kk = (c % (SA_K / 2)) * 2;
     const int64_t row = r0 + r;
+    // the loads do not wait for the exponent: a row marked non-finite is
+    // zeroed after them
     double x0 = 0.0, x1 = 0.0;
-    if (row < m && e[row] != OZAKI_NONFINITE) {
-      const int sh = -e[row];
-      if (k0 + kk < k) x0 = ldexp(A[row * lda + k0 + kk], sh);
-      if (k0 + kk + 1 < k) x1 = ldexp(A[row * lda + k0 + kk + 1], sh);
+    if (row < m) {
+      const double a0 = k0 + kk < k ? A[row * lda + k0 + kk] : 0.0;
+      const double a1 = k0 + kk + 1 < k ? A[row * lda + k0 + kk + 1] : 0.0;
+      const int er = e[row];
+      if (er != OZAKI_NONFINITE) {
+        x0 = ldexp(a0, -er);
+        x1 = ldexp(a1, -er);
+      }
     }
     tile[r][kk] = x0;
     tile[r][kk + 1] = x1;
@@ -186,15 +194,13 @@ __global__ __launch_bounds__(256) void slice_b_kernel(const double* __restrict__
   if (id >= cols * chunks) return;
   const int64_t kc = (id / cols) * 16, col = id - (id / cols) * cols;
   double x[16];
-  if (col < n && f[col] != OZAKI_NONFINITE) {
-    const int sh = -f[col];
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-      x[i] = (kc + i < k) ? ldexp(B[(kc + i) * ldb + col], sh) : 0.0;
-  } else {
+  for (int i = 0; i < 16; ++i) x[i] = (col < n && kc + i < k) ? B[(kc + i) * ldb + col] : 0.0;
+  // a column marked non-finite is zeroed after the loads (they do not wait
+  // for the exponent)
+  const int fc = col < n ? f[col] : 0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) x[i] = 0.0;
-  }
+  for (int i = 0; i < 16; ++i) x[i] = fc != OZAKI_NONFINITE ? ldexp(x[i], -fc) : 0.0;
   const int64_t rounds = kp / OZ_BK;
   const int64_t off = ((col / OZ_BN) * rounds + kc / OZ_BK) * (OZ_BN * OZ_BK) +
                       frag_offset((int)(col % OZ_BN), (int)((kc % OZ_BK) / 16));

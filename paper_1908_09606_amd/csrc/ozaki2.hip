@@ -108,9 +108,15 @@ __global__ __launch_bounds__(256) void residue_a_kernel(const double* __restrict
   for (int c = t; c < 64 * O2_BK; c += 256) {
     const int r = c >> 6, kk = c & 63;
     const int64_t row = rb * 64 + r, kt = R * O2_BK + kk;
+    // A row marked non-finite has e = OZAKI_NONFINITE: the shift then takes
+    // its finite entries to zero and leaves NaN / infinity, which the
+    // magnitude test zeroes (finite rows stay below 2^50).  Testing the
+    // value rather than the marker keeps the load independent of e[row].
     double x = 0.0;
-    if (row < m && kt < k && e[row] != OZAKI_NONFINITE)
+    if (row < m && kt < k) {
       x = rint(ldexp(A[row * lda + kt], cp.beta - e[row]));
+      x = fabs(x) <= 0x1p60 ? x : 0.0;
+    }
     tile[r][kk] = x;
   }
   __syncthreads();
@@ -142,8 +148,10 @@ __global__ __launch_bounds__(256) void residue_b_kernel(const double* __restrict
     const int kk = c >> 6, cc = c & 63;
     const int64_t col = cb * 64 + cc, kt = R * O2_BK + kk;
     double x = 0.0;
-    if (col < n && kt < k && f[col] != OZAKI_NONFINITE)
+    if (col < n && kt < k) {  // non-finite columns: as for the rows of A
       x = rint(ldexp(B[kt * ldb + col], cp.beta - f[col]));
+      x = fabs(x) <= 0x1p60 ? x : 0.0;
+    }
     tile[kk][cc] = x;
   }
   __syncthreads();

@@ -117,11 +117,17 @@ __global__ __launch_bounds__(256) void slice_a_bf16_kernel(const double* __restr
   for (int c = threadIdx.x; c < OB_BM * OB_BK / 2; c += 256) {
     const int r = c / (OB_BK / 2), kk = (c % (OB_BK / 2)) * 2;
     const int64_t row = r0 + r;
+    // the loads do not wait for the exponent: a row marked non-finite is
+    // zeroed after them
     double x0 = 0.0, x1 = 0.0;
-    if (row < m && e[row] != OZAKI_NONFINITE) {
-      const int sh = -e[row];
-      if (k0 + kk < k) x0 = ldexp(A[row * lda + k0 + kk], sh);
-      if (k0 + kk + 1 < k) x1 = ldexp(A[row * lda + k0 + kk + 1], sh);
+    if (row < m) {
+      const double a0 = k0 + kk < k ? A[row * lda + k0 + kk] : 0.0;
+      const double a1 = k0 + kk + 1 < k ? A[row * lda + k0 + kk + 1] : 0.0;
+      const int er = e[row];
+      if (er != OZAKI_NONFINITE) {
+        x0 = ldexp(a0, -er);
+        x1 = ldexp(a1, -er);
+      }
     }
     tile[r][kk] = x0;
     tile[r][kk + 1] = x1;
@@ -149,14 +155,13 @@ __global__ __launch_bounds__(256) void slice_b_bf16_kernel(const double* __restr
   if (id >= cols * chunks) return;
   const int64_t kc = (id / cols) * 8, col = id - (id / cols) * cols;
   double x[8];
-  if (col < n && f[col] != OZAKI_NONFINITE) {
-    const int sh = -f[col];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) x[i] = (kc + i < k) ? ldexp(B[(kc + i) * ldb + col], sh) : 0.0;
-  } else {
+  for (int i = 0; i < 8; ++i) x[i] = (col < n && kc + i < k) ? B[(kc + i) * ldb + col] : 0.0;
+  // a column marked non-finite is zeroed after the loads (they do not wait
+  // for the exponent)
+  const int fc = col < n ? f[col] : 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) x[i] = 0.0;
-  }
+  for (int i = 0; i < 8; ++i) x[i] = fc != OZAKI_NONFINITE ? ldexp(x[i], -fc) : 0.0;
   const int64_t rounds = kp / OB_BK;
   const int64_t off = ((col / OB_BN) * rounds + kc / OB_BK) * B_BLK +
                       frag_offset((int)(col % OB_BN), (int)((kc % OB_BK) / 8));

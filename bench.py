@@ -199,6 +199,15 @@ def main():
         "roofline": roofline,
         "shapes": shape_rows,
     }
+    # The paper's own figures, measured on a CPU cluster: context, not a
+    # baseline for this metric (hence vs_baseline is null).
+    sq = next((r for r in shape_rows if r["shape"] == "square"), None)
+    out["paper_context"] = {
+        "machine": "Piz Daint XC40 CPU partition (2 x 18-core Xeon E5-2695 v4 per node)",
+        "best_fraction_of_machine_peak": 0.88,
+        "square_16384_ms_on_9216_cores": 142.0,
+        "square_16384_ms_here": sq["ms_median"] if sq else None,
+    }
 
     if args.copy_calibration > 0:
         nel = args.copy_calibration // 8

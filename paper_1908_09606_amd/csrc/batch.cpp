@@ -33,6 +33,9 @@ namespace cosma {
 int batched_occupancy_f64(int tile_id);
 int batched_occupancy_f32(int tile_id);
 
+bool batched_form_f32(int tile_id);
+bool batched_form(int dtype, int tile_id) { return dtype == F64 || batched_form_f32(tile_id); }
+
 int batched_occupancy(int dtype, int tile_id) {
   return dtype == F64 ? batched_occupancy_f64(tile_id) : batched_occupancy_f32(tile_id);
 }
@@ -89,6 +92,7 @@ int policy_tile(int policy, int dtype, const BatchProblem& p, const cosma_device
       int best = 0;
       double best_t = INFINITY;
       for (int id = 0; id < cnt; ++id) {
+        if (!batched_form(dtype, id)) continue;
         const double t = batch_item_cost(p.m, p.n, p.k, dtype, id, f);
         if (t < best_t) {
           best_t = t;

@@ -1,6 +1,9 @@
 // FP32-class GEMMs on the CDNA4 matrix cores.
 //
-//   gemm_f32_kernel     native FP32: v_mfma_f32_16x16x4f32
+//   gemm_f32_kernel     native FP32: v_mfma_f32_16x16x4f32 on 16x16 blocks
+//                       or v_mfma_f32_32x32x2f32 on 32x32 blocks (the
+//                       widest tile, whose 64x64 wave blocks keep four
+//                       independent accumulator chains per wave)
 //   gemm_bf16x3_kernel  FP32-accurate product from bf16 pieces: every FP32
 //                       operand x is split as x_hi = bf16_rn(x),
 //                       x_lo = bf16_rn(x - x_hi) and
@@ -17,8 +20,10 @@
 // moves contiguous 16-byte chunks straight into the swizzled LDS layout
 // with no conversion arithmetic and no bounds checks in its main loop.
 //
-// Matrix-core layouts (lane l, r = l % 16, g = l / 16):
+// Matrix-core layouts (lane l, r = l % 16, g = l / 16, c = l % 32, q = l / 32):
 //   f32 16x16x4:  a = A[r][g], b = B[g][r], acc[v] = D[4g + v][r]
+//   f32 32x32x2:  a = A[c][q], b = B[q][c],
+//                 acc[v] = D[8 (v / 4) + 4q + v % 4][c] (v < 16)
 //   bf16 16x16x32: a[i] = A[r][8g + i], b[i] = B[8g + i][r] (i < 8),
 //                  acc[v] = D[4g + v][r]
 #include <hip/hip_runtime.h>
@@ -30,20 +35,24 @@ namespace cosma {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------------------- native FP32
-template <int BM, int BN, int BK, int WM, int WN>
+// BLK: edge of the matrix-core output block, 16 (16x16x4) or 32 (32x32x2).
+template <int BM, int BN, int BK, int WM, int WN, int BLK = 16>
 struct F32Tile {
   static constexpr int NT = WM * WN * 64;
   static constexpr int WTM = BM / WM, WTN = BN / WN;
-  static constexpr int MI = WTM / 16, NI = WTN / 16;
+  static constexpr int MI = WTM / BLK, NI = WTN / BLK;  // output blocks per wave
   static constexpr int LDA_S = BK + 4;   // As[row][k] (floats), 16-byte rows
   static constexpr int LDB_S = BN + 4;   // Bs[k][col]
   static constexpr int A_CHUNKS = BM * BK / 4 / NT;  // float4 per thread
   static constexpr int B_CHUNKS = BK * BN / 4 / NT;
   static constexpr int A_STAGE = BM * LDA_S, B_STAGE = BK * LDB_S;
+  static_assert(BLK == 16 || BLK == 32, "matrix-core form");
+  static_assert(WTM % BLK == 0 && WTN % BLK == 0, "wave blocks");
   static_assert(BK % 16 == 0 && (BM * BK / 4) % NT == 0 && (BK * BN / 4) % NT == 0, "tiling");
   static_assert(2 * (A_STAGE + B_STAGE) * 4 <= 160 * 1024, "LDS budget");
 };
@@ -159,66 +168,71 @@ __device__ __forceinline__ void f32_store(float* As, float* Bs, const f4 (&ra)[T
   }
 }
 
-// Epilogue shared by both FP32-class kernels (standard 16x16 output layout).
-template <int MI, int NI, int WTM, int WTN>
+// Epilogue shared by the FP32-class kernels.  Accumulator v of lane l in
+// the BLK x BLK output block holds row 8 (v / 4) + 4 (l / BLK) + v % 4,
+// column l % BLK (for BLK = 16, v < 4, this is the 16x16 layout above).
+template <int BLK, int MI, int NI, int WTM, int WTN, class V>
 __device__ __forceinline__ void f32_epilogue(const GemmArgs& g, const ItemCoord& ic, int64_t row0,
-                                             int64_t col0, int wm, int wn, int lr, int lg,
-                                             const f4 (&acc)[MI][NI]) {
-  if (g.splits == 1) {
-    float* __restrict__ C = static_cast<float*>(g.C);
-    const float alpha = (float)g.alpha, beta = (float)g.beta;
+                                             int64_t col0, int wm, int wn, int lane,
+                                             const V (&acc)[MI][NI]) {
+  constexpr int NV = BLK * BLK / 64;
+  const int lcol = lane % BLK, lrow = 4 * (lane / BLK);
+  const bool direct = g.splits == 1;
+  float* __restrict__ C = static_cast<float*>(g.C);
+  float* __restrict__ P = direct ? nullptr : static_cast<float*>(g.P) + ic.split * g.split_stride;
+  const float alpha = (float)g.alpha, beta = (float)g.beta;
 #pragma unroll
-    for (int i = 0; i < MI; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int j = 0; j < NI; ++j) {
-        const int64_t col = col0 + wn * WTN + j * 16 + lr;
+    for (int j = 0; j < NI; ++j) {
+      const int64_t col = col0 + wn * WTN + j * BLK + lcol;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t row = row0 + wm * WTM + i * 16 + lg * 4 + v;
-          if (row < g.m && col < g.n) {
+      for (int v = 0; v < NV; ++v) {
+        const int64_t row = row0 + wm * WTM + i * BLK + 8 * (v / 4) + lrow + v % 4;
+        if (row < g.m && col < g.n) {
+          if (direct) {
             float* p = C + row * g.ldc + col;
             const float r = alpha * acc[i][j][v];
             *p = beta != 0.0f ? r + beta * *p : r;
+          } else {
+            P[row * g.ldp + col] = acc[i][j][v];
           }
         }
       }
-  } else {
-    float* __restrict__ P = static_cast<float*>(g.P) + ic.split * g.split_stride;
-#pragma unroll
-    for (int i = 0; i < MI; ++i)
-#pragma unroll
-      for (int j = 0; j < NI; ++j) {
-        const int64_t col = col0 + wn * WTN + j * 16 + lr;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t row = row0 + wm * WTM + i * 16 + lg * 4 + v;
-          if (row < g.m && col < g.n) P[row * g.ldp + col] = acc[i][j][v];
-        }
-      }
-  }
+    }
 }
 
 // One work item: the BM x BN block (ic.tile_row, ic.tile_col) over the
-// reduction range of split ic.split.  As / Bs: two LDS stages each.
-template <int BM, int BN, int BK, int WM, int WN, bool FAST>
+// reduction range of split ic.split.  As / Bs: two LDS stages each.  Each
+// 16-k group of a round is split among the lanes so that every lane reads
+// contiguous k of its A row (one or two 16-byte LDS reads per block) and
+// every LDS element is read once per wave: in the 16x16x4 form lane group
+// g takes k = 4g + s (s < 4), in the 32x32x2 form lane half q takes
+// k = 8q + s (s < 8), instruction s pairing the two halves.
+template <int BM, int BN, int BK, int WM, int WN, int BLK, bool FAST>
 __device__ __forceinline__ void f32_tile_body(const GemmArgs& g, const ItemCoord& ic,
                                               float (*As)[F32Tile<BM, BN, BK, WM, WN>::A_STAGE],
                                               float (*Bs)[F32Tile<BM, BN, BK, WM, WN>::B_STAGE]) {
-  using TL = F32Tile<BM, BN, BK, WM, WN>;
+  using TL = F32Tile<BM, BN, BK, WM, WN, BLK>;
+  typedef float acc_t __attribute__((ext_vector_type(BLK * BLK / 64)));
   const int64_t row0 = ic.tile_row * BM, col0 = ic.tile_col * BN;
   const int64_t kbeg = ic.split * g.k_split;
   const int64_t kend = min64(g.k, kbeg + g.k_split);
   const int64_t nk = ceil_div(kend - kbeg, BK);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int lr = lane & 15, lg = lane >> 4;
+  const int lr = lane % BLK, lg = lane / BLK;  // block row / column, k group
+  constexpr int KS = BLK / 4;                  // k per lane group and 16-k group
+  static_assert(KS % 4 == 0 && KS * (64 / BLK) == 16, "k split of a 16-k group");
   const bool a_in = row0 + BM <= g.m, b_in = col0 + BN <= g.n;
 
-  f4 acc[TL::MI][TL::NI];
+  acc_t acc[TL::MI][TL::NI];
 #pragma unroll
   for (int i = 0; i < TL::MI; ++i)
 #pragma unroll
-    for (int j = 0; j < TL::NI; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TL::NI; ++j)
+#pragma unroll
+      for (int v = 0; v < BLK * BLK / 64; ++v) acc[i][j][v] = 0.f;
 
   f4 ra[TL::A_CHUNKS], rb[TL::B_CHUNKS];
   if (nk > 0) {
@@ -236,47 +250,55 @@ __device__ __forceinline__ void f32_tile_body(const GemmArgs& g, const ItemCoord
     const float* bs = Bs[cur];
 #pragma unroll
     for (int h = 0; h < BK / 16; ++h) {
-      f4 af[TL::MI];
-      float bf[TL::NI][4];
+      f4 af[TL::MI][KS / 4];
+      float bf[TL::NI][KS];
 #pragma unroll
       for (int i = 0; i < TL::MI; ++i)
-        af[i] = *reinterpret_cast<const f4*>(as + (wm * TL::WTM + i * 16 + lr) * TL::LDA_S +
-                                             h * 16 + lg * 4);
+#pragma unroll
+        for (int c = 0; c < KS / 4; ++c)
+          af[i][c] = *reinterpret_cast<const f4*>(as + (wm * TL::WTM + i * BLK + lr) * TL::LDA_S +
+                                                  h * 16 + lg * KS + c * 4);
 #pragma unroll
       for (int j = 0; j < TL::NI; ++j)
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-          bf[j][s] = bs[(h * 16 + lg * 4 + s) * TL::LDB_S + wn * TL::WTN + j * 16 + lr];
+        for (int s = 0; s < KS; ++s)
+          bf[j][s] = bs[(h * 16 + lg * KS + s) * TL::LDB_S + wn * TL::WTN + j * BLK + lr];
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int s = 0; s < KS; ++s)
 #pragma unroll
         for (int i = 0; i < TL::MI; ++i)
 #pragma unroll
-          for (int j = 0; j < TL::NI; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < TL::NI; ++j) {
+            if constexpr (BLK == 16)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s / 4][s % 4], bf[j][s],
+                                                               acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i][s / 4][s % 4], bf[j][s],
+                                                               acc[i][j], 0, 0, 0);
+          }
     }
     if (more) f32_store<TL, BM, BN, BK>(As[cur ^ 1], Bs[cur ^ 1], ra, rb);
     __syncthreads();
   }
-  f32_epilogue<TL::MI, TL::NI, TL::WTM, TL::WTN>(g, ic, row0, col0, wm, wn, lr, lg, acc);
+  f32_epilogue<BLK, TL::MI, TL::NI, TL::WTM, TL::WTN>(g, ic, row0, col0, wm, wn, lane, acc);
 }
 
 // The two loop bodies are compiled apart and chosen once per work item.
-template <int BM, int BN, int BK, int WM, int WN>
+template <int BM, int BN, int BK, int WM, int WN, int BLK>
 __device__ __forceinline__ void f32_tile(const GemmArgs& g, const ItemCoord& ic,
                                          float (*As)[F32Tile<BM, BN, BK, WM, WN>::A_STAGE],
                                          float (*Bs)[F32Tile<BM, BN, BK, WM, WN>::B_STAGE]) {
   const bool fast = (ic.tile_row + 1) * BM <= g.m && (ic.tile_col + 1) * BN <= g.n && g.vec_a &&
                     g.vec_b;
   if (fast)
-    f32_tile_body<BM, BN, BK, WM, WN, true>(g, ic, As, Bs);
+    f32_tile_body<BM, BN, BK, WM, WN, BLK, true>(g, ic, As, Bs);
   else
-    f32_tile_body<BM, BN, BK, WM, WN, false>(g, ic, As, Bs);
+    f32_tile_body<BM, BN, BK, WM, WN, BLK, false>(g, ic, As, Bs);
 }
 
 // WPE: waves per SIMD the register allocation must allow (the tile menu's
-// blocks per CU times WM * WN / 4).
-template <int BM, int BN, int BK, int WM, int WN, int WPE>
+// blocks per CU times WM * WN / 4).  BLK: matrix-core form (16 or 32).
+template <int BM, int BN, int BK, int WM, int WN, int WPE, int BLK>
 __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void gemm_f32_kernel(
     GemmArgs g) {
   using TL = F32Tile<BM, BN, BK, WM, WN>;
@@ -284,13 +306,13 @@ __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE
   __shared__ __attribute__((aligned(16))) float Bs[2][TL::B_STAGE];
   const int64_t l = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x, g.num_xcds);
   const ItemCoord ic = item_coord(l, g.tiles_m, g.tiles_n, g.group_m);
-  f32_tile<BM, BN, BK, WM, WN>(g, ic, As, Bs);
+  f32_tile<BM, BN, BK, WM, WN, BLK>(g, ic, As, Bs);
 }
 
 // Persistent batched form: every workgroup takes (problem, tile) items from
 // the device counter until the list is exhausted; each item is computed
 // exactly as by gemm_f32_kernel with one split.
-template <int BM, int BN, int BK, int WM, int WN, int WPE>
+template <int BM, int BN, int BK, int WM, int WN, int WPE, int BLK>
 __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void gemm_f32_batched_kernel(
     BatchArgs b) {
   using TL = F32Tile<BM, BN, BK, WM, WN>;
@@ -318,7 +340,7 @@ __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE
     ic.split = 0;
     ic.tile_row = item.tile / p.tiles_n;
     ic.tile_col = item.tile - ic.tile_row * p.tiles_n;
-    f32_tile<BM, BN, BK, WM, WN>(g, ic, As, Bs);
+    f32_tile<BM, BN, BK, WM, WN, BLK>(g, ic, As, Bs);
   }
 }
 
@@ -614,7 +636,7 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_bf16x3_kernel(X3Args g) {
   e.split_stride = g.split_stride;
   e.alpha = g.alpha;
   e.beta = g.beta;
-  f32_epilogue<TL::MI, TL::NI, TL::WTM, TL::WTN>(e, ic, row0, col0, wm, wn, lr, lg, acc);
+  f32_epilogue<16, TL::MI, TL::NI, TL::WTM, TL::WTN>(e, ic, row0, col0, wm, wn, lane, acc);
 }
 
 template <class K>
@@ -630,9 +652,10 @@ hipError_t launch_items(K kernel, int threads, const GemmArgs& g, hipStream_t s)
 
 hipError_t launch_gemm_f32(int tile_id, const GemmArgs& g, hipStream_t s) {
   switch (tile_id) {
-    case 0: return launch_items(gemm_f32_kernel<128, 128, 32, 4, 2, 4>, 512, g, s);
-    case 1: return launch_items(gemm_f32_kernel<64, 64, 32, 2, 2, 4>, 256, g, s);
-    case 2: return launch_items(gemm_f32_kernel<256, 128, 32, 4, 4, 4>, 1024, g, s);
+    case 0: return launch_items(gemm_f32_kernel<128, 128, 32, 4, 2, 4, 16>, 512, g, s);
+    case 1: return launch_items(gemm_f32_kernel<64, 64, 32, 2, 2, 4, 16>, 256, g, s);
+    case 2: return launch_items(gemm_f32_kernel<256, 128, 32, 4, 4, 4, 16>, 1024, g, s);
+    case 3: return launch_items(gemm_f32_kernel<256, 256, 32, 4, 4, 4, 32>, 1024, g, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -644,11 +667,15 @@ hipError_t launch_persistent(K kernel, int threads, const BatchArgs& b, int grid
   return hipGetLastError();
 }
 
+// Tiles with a persistent batched form: all but the 256 x 256 tile, whose
+// 64 accumulators per lane leave no room for the item loop's state.
+bool batched_form_f32(int tile_id) { return tile_id >= 0 && tile_id <= 2; }
+
 hipError_t launch_batched_f32(int tile_id, const BatchArgs& b, int grid, hipStream_t s) {
   switch (tile_id) {
-    case 0: return launch_persistent(gemm_f32_batched_kernel<128, 128, 32, 4, 2, 4>, 512, b, grid, s);
-    case 1: return launch_persistent(gemm_f32_batched_kernel<64, 64, 32, 2, 2, 4>, 256, b, grid, s);
-    case 2: return launch_persistent(gemm_f32_batched_kernel<256, 128, 32, 4, 4, 4>, 1024, b, grid, s);
+    case 0: return launch_persistent(gemm_f32_batched_kernel<128, 128, 32, 4, 2, 4, 16>, 512, b, grid, s);
+    case 1: return launch_persistent(gemm_f32_batched_kernel<64, 64, 32, 2, 2, 4, 16>, 256, b, grid, s);
+    case 2: return launch_persistent(gemm_f32_batched_kernel<256, 128, 32, 4, 4, 4, 16>, 1024, b, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -662,9 +689,9 @@ int occupancy_of(K kernel, int threads) {
 
 int batched_occupancy_f32(int tile_id) {
   switch (tile_id) {
-    case 0: return occupancy_of(gemm_f32_batched_kernel<128, 128, 32, 4, 2, 4>, 512);
-    case 1: return occupancy_of(gemm_f32_batched_kernel<64, 64, 32, 2, 2, 4>, 256);
-    case 2: return occupancy_of(gemm_f32_batched_kernel<256, 128, 32, 4, 4, 4>, 1024);
+    case 0: return occupancy_of(gemm_f32_batched_kernel<128, 128, 32, 4, 2, 4, 16>, 512);
+    case 1: return occupancy_of(gemm_f32_batched_kernel<64, 64, 32, 2, 2, 4, 16>, 256);
+    case 2: return occupancy_of(gemm_f32_batched_kernel<256, 128, 32, 4, 4, 4, 16>, 1024);
     default: return 1;
   }
 }

@@ -42,6 +42,7 @@ constexpr TileDesc kTilesF32[] = {
     {128, 128, 32, 512, 2, 0.86},
     {64, 64, 32, 256, 4, 0.70},
     {256, 128, 32, 1024, 1, 0.865},
+    {256, 256, 32, 1024, 1, 0.895},
 };
 constexpr TileDesc kTilesBf16x3[] = {
     {128, 128, 32, 256, 2, 0.48},

@@ -95,6 +95,25 @@ def test_graph_handle_bit_equal_to_single_launches(gpu, dtype, dist):
         assert cm.cosma_batch_destroy(h) == 0
 
 
+def test_f32_batch_uses_tiles_with_a_batched_form(gpu):
+    """The 256 x 256 FP32 tile (menu index 3) has no persistent batched form:
+    the batch cost model never gives it a problem, large ones included."""
+    import torch
+    dims = [(2048, 2048, 512), (1024, 4096, 256), (300, 200, 100)]
+    mats = make_batch(dims, synth.UNIFORM_F32, 400)
+    a = args_of(dims, mats, [1.0] * len(dims), [0.0] * len(dims))
+    rc, h = cm.cosma_batch_create(*a, cm.COSMA_F32)
+    assert rc == 0 and h
+    try:
+        rc, tiles = cm.cosma_batch_tiles(h, len(dims))
+        log(f"f32 batch tiles {tiles}")
+        assert rc == 0 and all(0 <= t <= 2 for t in tiles)
+        assert cm.cosma_batch_run(h) == 0
+        torch.cuda.synchronize()
+    finally:
+        assert cm.cosma_batch_destroy(h) == 0
+
+
 def test_graph_handle_beta_nonzero_against_oracle(gpu):
     import torch
     dims = [(130, 70, 300), (64, 200, 129), (5, 5, 5), (40, 50, 0)]

@@ -15,11 +15,13 @@ SHAPES = [(1, 1, 1), (1, 7, 3), (17, 33, 5), (64, 64, 32), (65, 63, 33), (130, 1
 
 
 @pytest.mark.parametrize("dtype,rng_int", [(F32, 8), (X3, 16)])
-@pytest.mark.parametrize("tile", range(3))
+@pytest.mark.parametrize("tile", range(4))
 def test_integer_exact_all_tiles_ragged(gpu, dtype, rng_int, tile):
     """Integer inputs: native FP32 sums stay below 2^24 (exact); for BF16x3
     integers |x| <= 16 are bf16-representable, so every lo piece is zero and
-    the three-product sum is exact as well."""
+    the three-product sum is exact as well.  Both menus hold four tiles
+    (native FP32 tile 3 is the 256 x 256 tile on 32x32x2 instructions)."""
+    assert cm.cosma_tile_count(dtype) == 4
     for (m, n, k) in SHAPES:
         log(f"{'f32' if dtype == F32 else 'bf16x3'} int tile {tile} {m}x{n}x{k}")
         lda, ldb, ldc = k + 3, n + 1, n + 2
@@ -42,7 +44,7 @@ def test_split_k_bit_identical_on_integers(gpu, dtype):
     exact = (Ah @ Bh).astype(np.float64)
     _, A = device_matrix(m, k, 9, synth.STREAM_A, synth.INT_F32, 8)
     _, B = device_matrix(k, n, 9, synth.STREAM_B, synth.INT_F32, 8)
-    for tile in range(3):
+    for tile in range(cm.cosma_tile_count(dtype)):
         for pk in (1, 2, 3, 5):
             log(f"dtype {dtype} split-k tile {tile} pk {pk}")
             _, C = device_matrix(m, n, 1, synth.STREAM_C, synth.UNIFORM_F32)

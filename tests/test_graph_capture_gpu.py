@@ -13,6 +13,7 @@ from gpu_util import device_matrix, log
 pytestmark = pytest.mark.gpu
 
 CASES = [("f64", (300, 257, 1000), 1), ("f64", (256, 128, 5000), 3), ("f32", (300, 257, 1000), 2),
+         ("f32", (600, 520, 900), 2, 3),
          ("bf16x3", (513, 300, 700), 1), ("ozaki", (300, 257, 1000), 1),
          ("ozaki2", (513, 300, 700), 1), ("ozaki2", (130, 140, 70000), 2),
          ("ozaki_bf16", (300, 257, 1000), 1), ("ozaki_bf16", (130, 140, 5000), 2)]
@@ -21,7 +22,8 @@ CASES = [("f64", (300, 257, 1000), 1), ("f64", (256, 128, 5000), 3), ("f32", (30
 @pytest.mark.parametrize("case", CASES)
 def test_replays_equal_eager(gpu, case):
     import torch
-    dtype, (m, n, k), p_k = case
+    dtype, (m, n, k), p_k = case[:3]
+    tile = case[3] if len(case) > 3 else 0
     f32 = dtype in ("f32", "bf16x3")
     dist = synth.UNIFORM_F32 if f32 else synth.UNIFORM_F64
     tdt = torch.float32 if f32 else torch.float64
@@ -29,7 +31,7 @@ def test_replays_equal_eager(gpu, case):
     _, A = device_matrix(m, k, 21, synth.STREAM_A, dist)
     _, B = device_matrix(k, n, 21, synth.STREAM_B, dist)
     _, C0 = device_matrix(m, n, 21, synth.STREAM_C, dist)
-    rc, plan = cm.cosma_plan_make(m, n, k, dtype, 0, p_k)
+    rc, plan = cm.cosma_plan_make(m, n, k, dtype, tile, p_k)
     assert rc == 0 and plan.p_k == p_k
     cm.ensure_workspace(plan.workspace_bytes)   # before capture: no allocation inside
     alpha, beta = 1.25, -0.5

@@ -166,6 +166,37 @@ COSMA_API int cosma_gemm_ex(int layout, int transa, int transb, int64_t m, int64
 COSMA_API int cosma_workspace_size_ex(int layout, int transa, int transb, int64_t m, int64_t n,
                                       int64_t k, int dtype, size_t* bytes);
 
+/* ScaLAPACK-style product for callers that hold their matrices in the
+   block-cyclic format: the paper's blocked layout is compatible with it
+   (section 7.6) and its library takes ScaLAPACK operands directly
+   (section 1).  Computes
+       sub(C) = alpha*op(sub(A))*op(sub(B)) + beta*sub(C),
+   where sub(X) is the block of the global matrix X that starts at the
+   1-based position (iX, jX).  op(sub(A)) is m x k, op(sub(B)) is k x n,
+   sub(C) is m x n, and transa / transb take cosma_transpose values.
+   Each desc* is a nine-entry ScaLAPACK array descriptor
+   {DTYPE_ = 1, CTXT_, M_, N_, MB_, NB_, RSRC_, CSRC_, LLD_}.  On one GPU the
+   process grid is 1 x 1, so every block is local and the device array is
+   the whole global matrix, column-major with leading dimension LLD_
+   (element (i, j) at (j - 1)*LLD_ + i - 1), for any MB_, NB_ >= 1.
+   The process grid must be 1 x 1: RSRC_ = CSRC_ = 0, and CTXT_ is not read.
+   COSMA_ERR_INVALID_ARG:
+     - a null descriptor, DTYPE_ != 1, M_ or N_ < 0, MB_ or NB_ < 1,
+       RSRC_ or CSRC_ != 0, LLD_ < max(1, M_);
+     - iX or jX < 1;
+     - a submatrix of non-zero extent that reaches past M_ or N_;
+     - any argument cosma_gemm_ex rejects.
+   The product then runs as cosma_gemm_ex with COSMA_COL_MAJOR on the blocks'
+   first elements, so the workspace it needs is cosma_workspace_size_ex's
+   for COSMA_COL_MAJOR with the same transa, transb, m, n, k and dtype.
+   Asynchrony and the other rules are as for cosma_gemm.  Only sub(C) is
+   written. */
+COSMA_API int cosma_pgemm(int transa, int transb, int64_t m, int64_t n, int64_t k, double alpha,
+                          const void* A, int64_t ia, int64_t ja, const int32_t* desca,
+                          const void* B, int64_t ib, int64_t jb, const int32_t* descb,
+                          double beta, void* C, int64_t ic, int64_t jc, const int32_t* descc,
+                          int dtype, void* stream);
+
 /* ---- batches of independent products (Algorithm 1's "for all p_i in
    parallel" over many small problems) ------------------------------------ */
 

@@ -39,7 +39,7 @@ COSMA_ERR_UNSUPPORTED = -4
 COSMA_ERR_NO_MEMORY = -5
 
 EXPORTED = [
-    "cosma_gemm", "cosma_gemm_planned", "cosma_gemm_ex", "cosma_workspace_size_ex",
+    "cosma_gemm", "cosma_gemm_planned", "cosma_gemm_ex", "cosma_workspace_size_ex", "cosma_pgemm",
     "cosma_gemm_batched", "cosma_batch_create",
     "cosma_batch_run", "cosma_batch_destroy", "cosma_batch_info", "cosma_batch_tiles", "cosma_plan_query", "cosma_plan_query_facts",
     "cosma_plan_make", "cosma_plan_set_slices", "cosma_ozaki2_params", "cosma_tile_count", "cosma_tile_shape", "cosma_device_query",
@@ -99,6 +99,7 @@ def lib():
             L = ctypes.CDLL(LIB_PATH)
             i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
             pi64, pdbl, ppv = ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.POINTER(vp)
+            pi32 = ctypes.POINTER(ctypes.c_int32)
             P = ctypes.POINTER(cosma_plan_info)
             sig = {
                 "cosma_gemm": (i32, [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, vp]),
@@ -107,6 +108,8 @@ def lib():
                                         vp, i64, i32, vp]),
                 "cosma_workspace_size_ex": (i32, [i32, i32, i32, i64, i64, i64, i32,
                                                   ctypes.POINTER(ctypes.c_size_t)]),
+                "cosma_pgemm": (i32, [i32, i32, i64, i64, i64, dbl, vp, i64, i64, pi32, vp, i64,
+                                      i64, pi32, dbl, vp, i64, i64, pi32, i32, vp]),
                 "cosma_gemm_batched": (i32, [i64, pi64, pi64, pi64, pdbl, ppv, pi64, ppv, pi64,
                                              pdbl, ppv, pi64, i32, vp]),
                 "cosma_batch_create": (i32, [i64, pi64, pi64, pi64, pdbl, ppv, pi64, ppv, pi64,
@@ -208,6 +211,23 @@ def cosma_gemm_ex(layout, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, 
     return lib().cosma_gemm_ex(int(layout), int(transa), int(transb), m, n, k, float(alpha),
                                _ptr(A), lda, _ptr(B), ldb, float(beta), _ptr(C), ldc,
                                _dtype(dtype), _stream(stream))
+
+
+def descinit(m, n, mb, nb, lld):
+    """ScaLAPACK array descriptor of an m x n dense matrix on the 1 x 1 grid
+    (DTYPE_ 1, context 0, first block on process row / column 0)."""
+    return [1, 0, int(m), int(n), int(mb), int(nb), 0, 0, int(lld)]
+
+
+def _desc(d):
+    return None if d is None else (ctypes.c_int32 * len(d))(*[int(x) for x in d])
+
+
+def cosma_pgemm(transa, transb, m, n, k, alpha, A, ia, ja, desca, B, ib, jb, descb, beta, C, ic,
+                jc, descc, dtype, stream=None) -> int:
+    return lib().cosma_pgemm(int(transa), int(transb), m, n, k, float(alpha), _ptr(A), ia, ja,
+                             _desc(desca), _ptr(B), ib, jb, _desc(descb), float(beta), _ptr(C),
+                             ic, jc, _desc(descc), _dtype(dtype), _stream(stream))
 
 
 def cosma_workspace_size_ex(layout, transa, transb, m, n, k, dtype):

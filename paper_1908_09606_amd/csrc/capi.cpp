@@ -346,6 +346,29 @@ bool products_needed(const ExArgs& e, double alpha) {
   return e.m > 0 && e.n > 0 && e.k > 0 && alpha != 0.0;
 }
 
+// ScaLAPACK array descriptor of a dense matrix: DTYPE_, CTXT_, M_, N_, MB_,
+// NB_, RSRC_, CSRC_, LLD_.
+enum { DESC_DTYPE = 0, DESC_M = 2, DESC_N = 3, DESC_MB = 4, DESC_NB = 5, DESC_RSRC = 6,
+       DESC_CSRC = 7, DESC_LLD = 8 };
+
+// The rows x cols block of a descriptor-described matrix that starts at the
+// 1-based global position (i, j).  On a 1 x 1 process grid every block of the
+// block-cyclic distribution is local and the local array is the whole matrix,
+// column-major with leading dimension LLD_, whatever MB_ and NB_ are; *sub is
+// the block's first element (null if X is null).
+int sub_block(const void* X, int64_t i, int64_t j, const int32_t* desc, int64_t rows, int64_t cols,
+              size_t el, const void** sub, int64_t* ld) {
+  if (!desc || desc[DESC_DTYPE] != 1) return COSMA_ERR_INVALID_ARG;
+  const int64_t M = desc[DESC_M], N = desc[DESC_N], lld = desc[DESC_LLD];
+  if (M < 0 || N < 0 || desc[DESC_MB] < 1 || desc[DESC_NB] < 1) return COSMA_ERR_INVALID_ARG;
+  if (desc[DESC_RSRC] != 0 || desc[DESC_CSRC] != 0) return COSMA_ERR_INVALID_ARG;
+  if (lld < (M > 1 ? M : 1) || i < 1 || j < 1) return COSMA_ERR_INVALID_ARG;
+  if (rows > 0 && cols > 0 && (i - 1 + rows > M || j - 1 + cols > N)) return COSMA_ERR_INVALID_ARG;
+  *ld = lld;
+  *sub = X ? static_cast<const char*>(X) + ((j - 1) * lld + (i - 1)) * (int64_t)el : nullptr;
+  return COSMA_OK;
+}
+
 }  // namespace
 
 }  // namespace cosma
@@ -458,6 +481,26 @@ int cosma_workspace_size_ex(int layout, int transa, int transb, int64_t m, int64
   *bytes = (e.ta || e.tb) && e.m > 0 && e.n > 0 && e.k > 0 ? ex_workspace(plan, e, dtype)
                                                             : plan.workspace_bytes;
   return COSMA_OK;
+}
+
+int cosma_pgemm(int transa, int transb, int64_t m, int64_t n, int64_t k, double alpha,
+                const void* A, int64_t ia, int64_t ja, const int32_t* desca, const void* B,
+                int64_t ib, int64_t jb, const int32_t* descb, double beta, void* C, int64_t ic,
+                int64_t jc, const int32_t* descc, int dtype, void* stream) {
+  if (dtype < 0 || dtype >= NUM_DTYPES || m < 0 || n < 0 || k < 0) return COSMA_ERR_INVALID_ARG;
+  if ((transa != COSMA_NO_TRANS && transa != COSMA_TRANS) ||
+      (transb != COSMA_NO_TRANS && transb != COSMA_TRANS))
+    return COSMA_ERR_INVALID_ARG;
+  const size_t el = (size_t)word_bytes(dtype);
+  const bool ta = transa == COSMA_TRANS, tb = transb == COSMA_TRANS;
+  const void *a = nullptr, *b = nullptr, *c = nullptr;
+  int64_t lda = 0, ldb = 0, ldc = 0;
+  int rc = sub_block(A, ia, ja, desca, ta ? k : m, ta ? m : k, el, &a, &lda);
+  if (rc == COSMA_OK) rc = sub_block(B, ib, jb, descb, tb ? n : k, tb ? k : n, el, &b, &ldb);
+  if (rc == COSMA_OK) rc = sub_block(C, ic, jc, descc, m, n, el, &c, &ldc);
+  if (rc != COSMA_OK) return rc;
+  return cosma_gemm_ex(COSMA_COL_MAJOR, transa, transb, m, n, k, alpha, a, lda, b, ldb, beta,
+                       const_cast<void*>(c), ldc, dtype, stream);
 }
 
 int cosma_plan_query(int64_t m, int64_t n, int64_t k, int dtype, cosma_plan_info* out) {

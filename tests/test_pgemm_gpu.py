@@ -1,0 +1,112 @@
+"""cosma_pgemm on the GPU: products of sub-blocks of ScaLAPACK-described
+(column-major, 1 x 1 grid) matrices.  Exact on integer data, within the
+bound on uniform data, and nothing outside sub(C) is written."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_1908_09606_amd as cm
+from gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+N, T = cm.COSMA_NO_TRANS, cm.COSMA_TRANS
+
+
+def global_matrix(M, Nc, lld, seed, stream, dist, param, torch_dtype):
+    """A column-major M x Nc matrix with leading dimension lld: the device
+    buffer is Nc x lld row-major (column j is buffer row j); rows M..lld-1 of
+    every column hold values too, so a stray write shows.  Returns the host
+    copy of the buffer and the device buffer."""
+    import torch
+    H = synth.gen(Nc, lld, seed, stream, dist, param)
+    return H, torch.as_tensor(np.ascontiguousarray(H), dtype=torch_dtype).cuda()
+
+
+def block(H, i, j, rows, cols):
+    """Global block starting at 1-based (i, j) of the column-major matrix whose
+    buffer is H (rows x cols, as a float64 array)."""
+    return H[j - 1:j - 1 + cols, i - 1:i - 1 + rows].T.astype(np.float64)
+
+
+def run_p(ta, tb, m, n, k, alpha, beta, pos, dims, dist, param, dtype, torch_dtype, seed):
+    """pos: (ia, ja, ib, jb, ic, jc); dims: ((MA, NA, LLDA), (MB, NB, LLDB), (MC, NC, LLDC))."""
+    import torch
+    (ia, ja, ib, jb, ic, jc) = pos
+    (MA, NA, LA), (MB_, NB_, LB), (MC, NC, LC) = dims
+    HA, A = global_matrix(MA, NA, LA, seed, synth.STREAM_A, dist, param, torch_dtype)
+    HB, B = global_matrix(MB_, NB_, LB, seed, synth.STREAM_B, dist, param, torch_dtype)
+    HC, C = global_matrix(MC, NC, LC, seed, synth.STREAM_C, dist, param, torch_dtype)
+    da, db, dc = cm.descinit(MA, NA, 32, 64, LA), cm.descinit(MB_, NB_, 7, 5, LB), \
+        cm.descinit(MC, NC, 64, 32, LC)
+    rc, ws = cm.cosma_workspace_size_ex(cm.COSMA_COL_MAJOR, ta, tb, m, n, k, dtype)
+    assert rc == 0
+    cm.ensure_workspace(max(ws, 1))
+    rc = cm.cosma_pgemm(ta, tb, m, n, k, alpha, A, ia, ja, da, B, ib, jb, db, beta, C, ic, jc, dc,
+                        dtype)
+    assert rc == 0, cm.cosma_status_string(rc)
+    torch.cuda.synchronize()
+    opA = block(HA, ia, ja, *((k, m) if ta == T else (m, k)))
+    opA = opA.T if ta == T else opA
+    opB = block(HB, ib, jb, *((n, k) if tb == T else (k, n)))
+    opB = opB.T if tb == T else opB
+    return HC, C.double().cpu().numpy(), opA, opB
+
+
+COMBOS = [(ta, tb) for ta in (N, T) for tb in (N, T)]
+# (m, n, k, positions, global dims (M_, N_, LLD_) of A, B, C)
+CASES = [
+    (70, 45, 33, (3, 5, 2, 4, 7, 1), ((90, 90, 97), (90, 90, 90), (80, 60, 85))),
+    (257, 130, 300, (1, 1, 1, 1, 1, 1), ((310, 310, 311), (310, 310, 313), (257, 130, 257))),
+    (1, 1, 1, (5, 5, 5, 5, 5, 5), ((9, 9, 9), (9, 9, 10), (9, 9, 12))),
+]
+
+
+@pytest.mark.parametrize("ta,tb", COMBOS)
+@pytest.mark.parametrize("dtype,dist,tdt", [("f64", synth.INT_F64, "float64"),
+                                            ("f32", synth.INT_F32, "float32")])
+def test_sub_blocks_integer_exact(gpu, ta, tb, dtype, dist, tdt):
+    import torch
+    for ci, (m, n, k, pos, dims) in enumerate(CASES):
+        log(f"pgemm {dtype} ta={ta} tb={tb} {m}x{n}x{k} at {pos}")
+        alpha, beta = 2.0, -1.0
+        HC, out, opA, opB = run_p(ta, tb, m, n, k, alpha, beta, pos, dims, dist, 8, dtype,
+                                  getattr(torch, tdt), 30 + ci)
+        ic, jc = pos[4], pos[5]
+        expect = HC.astype(np.float64).copy()
+        sub = expect[jc - 1:jc - 1 + n, ic - 1:ic - 1 + m]
+        ref = alpha * (opA.astype(np.int64) @ opB.astype(np.int64)) + beta * sub.T
+        expect[jc - 1:jc - 1 + n, ic - 1:ic - 1 + m] = ref.T
+        assert np.array_equal(out, expect), (dtype, ta, tb, m, n, k)
+
+
+@pytest.mark.parametrize("ta,tb", COMBOS)
+def test_sub_blocks_uniform_within_bound(gpu, ta, tb):
+    import torch
+    m, n, k, pos, dims = 200, 150, 700, (11, 3, 5, 9, 2, 17), ((720, 720, 730), (720, 720, 721),
+                                                             (210, 170, 211))
+    log(f"pgemm f64 uniform ta={ta} tb={tb} {m}x{n}x{k}")
+    HC, out, opA, opB = run_p(ta, tb, m, n, k, 1.0, 0.0, pos, dims, synth.UNIFORM_F64, 0, "f64",
+                              torch.float64, 7)
+    ic, jc = pos[4], pos[5]
+    ref, D = oracle.gemm(opA, opB)
+    got = out[jc - 1:jc - 1 + n, ic - 1:ic - 1 + m].T
+    err = oracle.normalised_err(got, ref, D)
+    assert err <= oracle.fp64_bound(k), err
+    # everything outside sub(C) is as it was
+    mask = np.ones_like(out, dtype=bool)
+    mask[jc - 1:jc - 1 + n, ic - 1:ic - 1 + m] = False
+    assert np.array_equal(out[mask], HC.astype(np.float64)[mask])
+
+
+def test_emulated_dtype_through_descriptors(gpu):
+    """The descriptor adapter is dtype-agnostic: Ozaki II on integer data."""
+    import torch
+    m, n, k, pos, dims = 100, 90, 400, (2, 3, 4, 5, 6, 7), ((120, 420, 125), (100, 410, 104),
+                                                           (120, 110, 120))
+    HC, out, opA, opB = run_p(N, T, m, n, k, 1.0, 0.0, pos, dims, synth.INT_F64, 8, "ozaki2",
+                              torch.float64, 3)
+    ic, jc = pos[4], pos[5]
+    got = out[jc - 1:jc - 1 + n, ic - 1:ic - 1 + m].T
+    assert np.array_equal(got, (opA.astype(np.int64) @ opB.astype(np.int64)).astype(np.float64))

@@ -177,3 +177,17 @@ def test_ozaki_bf16_plan_and_workspace():
     rc, q = cm.cosma_plan_query(8192, 8192, 8192, "ozaki")
     rc, b = cm.cosma_plan_query(8192, 8192, 8192, "ozaki_bf16")
     assert b.predicted_ms > q.predicted_ms
+
+
+def test_f32_menu_and_wide_tile_choice():
+    """The FP32 menu's fourth tile is 256 x 256 (32x32x2 instructions); the
+    planner takes it for large squares and long reductions, and keeps the
+    smaller tiles where 256 x 256 blocks would leave CUs idle."""
+    assert cm.cosma_tile_count("f32") == 4
+    assert cm.cosma_tile_shape("f32", 3) == (0, (256, 256, 32))
+    for shape in [(16384, 16384, 16384), (8192, 8192, 8192), (4096, 4096, 1 << 18)]:
+        rc, p = cm.cosma_plan_query(*shape, "f32")
+        assert rc == 0 and (p.tile_m, p.tile_n) == (256, 256), shape
+    for shape in [(1000, 1000, 1000), (4097, 4095, 4093), (300, 257, 1000)]:
+        rc, p = cm.cosma_plan_query(*shape, "f32")
+        assert rc == 0 and (p.tile_m, p.tile_n) != (256, 256), shape

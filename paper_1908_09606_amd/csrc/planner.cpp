@@ -188,39 +188,83 @@ double io_count(int64_t m, int64_t n, int64_t k, int64_t tm, int64_t tn, int64_t
   return operands + out;
 }
 
+namespace {
+
+// Elements covered by the tiles [t0, t1) of an extent `total` cut into
+// `tiles` tiles of `t` (only the last tile can be partial).
+double span_elems(int64_t t0, int64_t t1, int64_t tiles, int64_t t, int64_t total) {
+  if (t1 <= t0) return 0.0;
+  double e = (double)(t1 - t0) * (double)t;
+  if (t1 == tiles) e -= (double)(tiles * t - total);
+  return e;
+}
+
+}  // namespace
+
+// Each wave of an XCD (slots_per_xcd consecutive items of its chunk) reads
+// every distinct A row-panel and B column-panel its items touch once.  The
+// distinct panels follow from the raster without visiting items: inside one
+// split, a run of items of one raster group touches a cyclic run of the
+// group's rows (all of them once the run is as long as the group is tall)
+// and one contiguous range of columns; groups have disjoint rows, and their
+// column ranges are merged.  The cost is one step per group a wave touches.
 double q_ea_bytes(int64_t m, int64_t n, int64_t k, int64_t k_split, int64_t splits, int tm,
                   int tn, int group_m, int64_t slots_per_xcd, int num_xcds, double w_bytes) {
   const int64_t tiles_m = ceil_div(m, tm), tiles_n = ceil_div(n, tn);
-  const int64_t items = tiles_m * tiles_n * splits;
+  const int64_t T = tiles_m * tiles_n;
+  const int64_t items = T * splits;
+  if (items <= 0) return 0.0;
   const int X = std::max(1, num_xcds);
+  const int64_t slots = std::max<int64_t>(1, slots_per_xcd);
+  const int64_t gsz = std::max(1, group_m);
+  const int64_t per_group = gsz * tiles_n;
   const int64_t q = items / X, r = items % X;
   double bytes = 0.0;
-  std::vector<int64_t> rows, cols;
+  std::vector<std::pair<int64_t, int64_t>> cols;
   for (int x = 0; x < X; ++x) {
     const int64_t begin = x * q + std::min<int64_t>(x, r);
     const int64_t count = q + (x < r ? 1 : 0);
-    for (int64_t w0 = 0; w0 < count; w0 += slots_per_xcd) {
-      const int64_t w1 = std::min(count, w0 + slots_per_xcd);
-      rows.clear();
-      cols.clear();
-      for (int64_t l = begin + w0; l < begin + w1; ++l) {
-        const ItemCoord c = item_coord(l, tiles_m, tiles_n, group_m);
-        rows.push_back(c.split * tiles_m + c.tile_row);
-        cols.push_back(c.split * tiles_n + c.tile_col);
-      }
-      std::sort(rows.begin(), rows.end());
-      std::sort(cols.begin(), cols.end());
-      rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
-      cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
-      for (int64_t key : rows) {
-        const int64_t tr = key % tiles_m, sp = key / tiles_m;
+    for (int64_t w0 = 0; w0 < count; w0 += slots) {
+      const int64_t a = begin + w0, b = begin + std::min(count, w0 + slots);
+      for (int64_t sp = a / T; sp * T < b; ++sp) {
+        const int64_t ta = std::max(a, sp * T) - sp * T, tb = std::min(b, (sp + 1) * T) - sp * T;
         const int64_t klen = std::min<int64_t>(k_split, k - sp * k_split);
-        bytes += (double)std::min<int64_t>(tm, m - tr * tm) * (double)klen * w_bytes;
-      }
-      for (int64_t key : cols) {
-        const int64_t tc = key % tiles_n, sp = key / tiles_n;
-        const int64_t klen = std::min<int64_t>(k_split, k - sp * k_split);
-        bytes += (double)std::min<int64_t>(tn, n - tc * tn) * (double)klen * w_bytes;
+        double row_elems = 0.0;
+        cols.clear();
+        for (int64_t g = ta / per_group; g * per_group < tb; ++g) {
+          const int64_t first = g * gsz, gm = std::min(tiles_m - first, gsz);
+          const int64_t g0 = g * per_group;
+          const int64_t ia = std::max(ta, g0) - g0, ib = std::min(tb, g0 + gm * tiles_n) - g0;
+          if (ib <= ia) continue;
+          // rows: item `in` of the group has row first + in % gm
+          if (ib - ia >= gm) {
+            row_elems += span_elems(first, first + gm, tiles_m, tm, m);
+          } else {
+            const int64_t r0 = ia % gm, r1 = r0 + (ib - ia);
+            if (r1 <= gm) {
+              row_elems += span_elems(first + r0, first + r1, tiles_m, tm, m);
+            } else {
+              row_elems += span_elems(first + r0, first + gm, tiles_m, tm, m);
+              row_elems += span_elems(first, first + r1 - gm, tiles_m, tm, m);
+            }
+          }
+          // columns: item `in` of the group has column in / gm
+          cols.emplace_back(ia / gm, (ib - 1) / gm + 1);
+        }
+        std::sort(cols.begin(), cols.end());
+        double col_elems = 0.0;
+        int64_t c0 = -1, c1 = -1;
+        for (const auto& c : cols) {
+          if (c.first > c1) {
+            col_elems += span_elems(c0, c1, tiles_n, tn, n);
+            c0 = c.first;
+            c1 = c.second;
+          } else {
+            c1 = std::max(c1, c.second);
+          }
+        }
+        col_elems += span_elems(c0, c1, tiles_n, tn, n);
+        bytes += (row_elems + col_elems) * (double)klen * w_bytes;
       }
     }
   }

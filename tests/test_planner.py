@@ -191,3 +191,32 @@ def test_f32_menu_and_wide_tile_choice():
     for shape in [(1000, 1000, 1000), (4097, 4095, 4093), (300, 257, 1000)]:
         rc, p = cm.cosma_plan_query(*shape, "f32")
         assert rc == 0 and (p.tile_m, p.tile_n) != (256, 256), shape
+
+
+def test_plan_cache_under_concurrent_queries():
+    """The plan cache is shared and mutex-guarded: eight threads querying
+    overlapping and distinct shapes (enough distinct ones to force the
+    cache's clearing) get exactly the plans a serial pass produces."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    rng = np.random.default_rng(11)
+    # more distinct (shape, dtype) keys than the cache's 4096 entries
+    shapes = [tuple(int(x) for x in rng.integers(1, 3000, size=3)) for _ in range(4200)]
+    shapes += [(16384, 16384, 16384), (2048, 2048, 1 << 20), (300, 257, 1000)] * 50
+    dtypes = ["f64", "f32", "bf16x3", "ozaki2"]
+    fields = [f for f, _ in cm.cosma_plan_info._fields_]
+
+    def plan(i):
+        rc, p = cm.cosma_plan_query(*shapes[i], dtypes[i % len(dtypes)])
+        assert rc == 0
+        return tuple(getattr(p, f) for f in fields)
+
+    serial = [plan(i) for i in range(len(shapes))]
+    order = list(range(len(shapes))) * 2
+    rng.shuffle(order)
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        got = list(ex.map(plan, order))
+    for i, g in zip(order, got):
+        assert g == serial[i], shapes[i]

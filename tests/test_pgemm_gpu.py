@@ -110,3 +110,25 @@ def test_emulated_dtype_through_descriptors(gpu):
     ic, jc = pos[4], pos[5]
     got = out[jc - 1:jc - 1 + n, ic - 1:ic - 1 + m].T
     assert np.array_equal(got, (opA.astype(np.int64) @ opB.astype(np.int64)).astype(np.float64))
+
+
+def test_quick_returns_through_descriptors(gpu):
+    """k = 0: sub(C) = beta * sub(C), nothing else written, A and B never
+    read (null pointers); m = 0: nothing written."""
+    import torch
+    M, Nc, L = 40, 30, 45
+    HC, C = global_matrix(M, Nc, L, 9, synth.STREAM_C, synth.INT_F64, 8, torch.float64)
+    # LLD_ of A still obeys lda >= m although A is not read
+    dA, dB, dC = cm.descinit(20, 10, 4, 4, 20), cm.descinit(10, 10, 4, 4, 10), \
+        cm.descinit(M, Nc, 8, 8, L)
+    m, n, ic, jc = 12, 7, 5, 9
+    assert cm.cosma_pgemm(N, N, m, n, 0, 1.0, None, 1, 1, dA, None, 1, 1, dB, -2.0, C, ic, jc, dC,
+                          "f64") == 0
+    torch.cuda.synchronize()
+    expect = HC.astype(np.float64).copy()
+    expect[jc - 1:jc - 1 + n, ic - 1:ic - 1 + m] *= -2.0
+    assert np.array_equal(C.cpu().numpy(), expect)
+    assert cm.cosma_pgemm(N, N, 0, n, 5, 1.0, None, 1, 1, dA, None, 1, 1, dB, 3.0, C, ic, jc, dC,
+                          "f64") == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy(), expect)

@@ -296,6 +296,7 @@ def run_variants(torch, cm, synth, dev, stream, keep, reps=20):
         f32, x3 = res["f32"], res["bf16x3"]
         rows.append({"shape": f"{m}x{n}x{k}", "f32_ms": round(f32[0], 3), "f32_ms_ci95": f32[3],
                      "f32_tflops": round(f32[1], 2), "f32_frac_peak": round(f32[1] / PEAK_F32, 4),
+                     "f32_tile": f"{f32[2].tile_m}x{f32[2].tile_n}", "f32_p_k": f32[2].p_k,
                      "bf16x3_ms": round(x3[0], 3), "bf16x3_ms_ci95": x3[3],
                      "bf16x3_tflops": round(x3[1], 2),
                      "bf16x3_frac_bf16_peak": round(3 * x3[1] / PEAK_BF16, 4),

@@ -5,7 +5,7 @@
  *
  * The product computed is the classical one of section 2.4 (A is m x k,
  * B is k x n, C is m x n), entry by entry the sum over the reduction index
- * of the CDAG update rule of section 4.1; only the order of that sum differs
+ * of the CDAG update rule of section 5.1; only the order of that sum differs
  * between schedules.  Algorithm 1 gives the structure of every call: pick the
  * sequential schedule (section 5), parallelise it (eq. optTileShape,
  * section 6.3), fit it to the processors (section 7.1), stream the
@@ -28,7 +28,8 @@
  *    NULL for the default stream) and returns once the work is enqueued.
  *  - Errors are returned as negative cosma_status values; on an argument
  *    error nothing is enqueued.  No entry point allocates device memory on
- *    the compute path; partial results live in the caller's workspace.
+ *    the compute path (cosma_batch_create allocates the handle's memory once,
+ *    at creation); partial results live in the caller's workspace.
  *  - Calls that share the registered workspace must be ordered on one
  *    stream (or synchronised by the caller).
  */
@@ -130,7 +131,42 @@ typedef struct {
   double thm2_words;          /* Theorem 2 bound per CU, words */
   double predicted_ms;        /* planner time model */
   size_t workspace_bytes;     /* device workspace the plan needs */
+  /* Error contract of the Ozaki dtypes (0 for the native dtypes), see
+     "Accuracy of the Ozaki dtypes" below. */
+  double err_scaled;          /* E: bound per unit |alpha| k 2^(e_i + f_j) */
+  double err_rounding;        /* G: bound per unit D_ij */
+  double spread_limit;        /* largest spread rho_ij with E rho + G <= 3k 2^-53 */
 } cosma_plan_info;
+
+/* Accuracy of the Ozaki dtypes.  The paper fixes no precision; the stated
+   target for FP64-class results is a normalised error
+       max_ij |C^_ij - C_ref_ij| / D_ij <= 4k 2^-53,
+       D_ij = |alpha| sum_t |A_it| |B_tj| + |beta| |C0_ij|,
+   against a binary64 reference C_ref.  Write e_i for the exponent of the
+   largest |A_it| of row i (max_t |A_it| < 2^e_i, as frexp gives it), f_j
+   likewise for column j of B, and C_ij for the exact result.  For finite
+   inputs whose scaled results stay in the normal binary64 range, every
+   Ozaki plan guarantees
+       |C^_ij - C_ij| <= |alpha| err_scaled k 2^(e_i + f_j) + err_rounding D_ij,
+   err_scaled coming from the finite number of slices (moduli) and
+   err_rounding from the binary64 steps.  With the spread of an entry
+       rho_ij = |alpha| k 2^(e_i + f_j) / D_ij   (>= 1 for dense rows),
+   the normalised error against the exact product is at most
+   err_scaled rho_ij + err_rounding, so it stays within 3k 2^-53 (and
+   within 4k 2^-53 of any binary64 reference that is itself within
+   k 2^-53 of the exact product) for every entry with
+   rho_ij <= spread_limit.  The planner picks the smallest slice count
+   (COSMA_F64_OZAKI_I8, COSMA_F64_OZAKI_BF16: 1..8) or number of moduli
+   (COSMA_F64_OZAKI2_I8: 2..16) whose spread_limit reaches the target spread
+   (cosma_set_ozaki_spread; default 2048: for entries sign * U[1,2) * 2^e,
+   e uniform in [-20, 20], rho_ij has a median of about 750 at k in the
+   thousands, and 2209 at most over an 8192^3 product); where no count
+   reaches it (short k: spread_limit grows about linearly with k), the
+   smallest count with the smallest err_scaled (the most accurate
+   emulation), and the plan's spread_limit then says which entries the
+   bound covers (0: none; the rounding term alone exceeds 3k 2^-53).  Uniform
+   [-1, 1] data has rho_ij of about 4.  Entries beyond spread_limit are
+   still within the absolute bound above; the call returns COSMA_OK. */
 
 /* ---- single product ---------------------------------------------------- */
 
@@ -200,29 +236,55 @@ COSMA_API int cosma_pgemm(int transa, int transb, int64_t m, int64_t n, int64_t 
 /* ---- batches of independent products (Algorithm 1's "for all p_i in
    parallel" over many small problems) ------------------------------------ */
 
-/* Variable-size batch: problem i is C_i = alpha_i*A_i*B_i + beta_i*C_i.  All
-   host arrays have length `count` and are read during the call only; the
-   batch runs as one persistent launch (the problems must not alias each
-   other's C).  Supported dtypes: COSMA_F32, COSMA_F64. */
+/* Variable-size batch: problem i is C_i = alpha_i*A_i*B_i + beta_i*C_i.
+   Every problem gets a tile and a split factor p_k from the planner's batch
+   model: a problem whose work items would be long against the batch's
+   share per resident workgroup is cut in k (section 6.2's rule that k is
+   cut once processors outnumber independent (i, j) domains), its partials
+   reduced in ascending split order.  The problems run as one persistent
+   launch per tile variant (the problems must not alias each other's C).
+   Supported dtypes: COSMA_F32, COSMA_F64 (else COSMA_ERR_UNSUPPORTED).
+   All host arrays have length `count` and are read during the call only.
+   The problem descriptors, the item map, the launch counters and the split
+   partials live in the registered workspace (cosma_set_workspace; size from
+   cosma_workspace_size_batched, COSMA_ERR_WORKSPACE when smaller): the call
+   allocates nothing, copies nothing from host memory (descriptors travel
+   inside kernel arguments), never waits for the device, and can be
+   captured into a HIP graph whose replays rerun the same batch.  Like
+   cosma_gemm, calls sharing the workspace must be ordered on one stream. */
 COSMA_API int cosma_gemm_batched(int64_t count, const int64_t* m, const int64_t* n, const int64_t* k,
                        const double* alpha, const void* const* A, const int64_t* lda,
                        const void* const* B, const int64_t* ldb, const double* beta,
                        void* const* C, const int64_t* ldc, int dtype, void* stream);
+/* Workspace bytes cosma_gemm_batched needs for these sizes (0 when no
+   problem has products).  Section 7.5's pre-allocated buffers: the caller
+   provides them once, the compute path never allocates. */
+COSMA_API int cosma_workspace_size_batched(int64_t count, const int64_t* m, const int64_t* n,
+                                           const int64_t* k, const double* alpha, int dtype,
+                                           size_t* bytes);
 
-/* Capture-once / replay-many batch: plans every problem, uploads the work
-   list and captures the launch into a HIP graph.  The handle owns its device
-   work list and graph until cosma_batch_destroy.  Pointers and sizes are
-   fixed at creation; replays read the current contents of A, B and C. */
+/* Capture-once / replay-many batch: plans every problem (tile and split),
+   uploads the descriptors and captures the launches into a HIP graph.  The
+   handle owns its device memory (allocated here, never on the replay path)
+   and graph until cosma_batch_destroy.  Pointers and sizes are fixed at
+   creation; replays read the current contents of A, B and C.  When every
+   beta is zero (and COSMA_AUTOTUNE is not 0) the autotuner runs the batch
+   once per candidate policy on `stream` and keeps the fastest. */
 COSMA_API int cosma_batch_create(int64_t count, const int64_t* m, const int64_t* n, const int64_t* k,
                        const double* alpha, const void* const* A, const int64_t* lda,
                        const void* const* B, const int64_t* ldb, const double* beta,
                        void* const* C, const int64_t* ldc, int dtype, void* stream,
                        void** handle);
+/* Launch the batch's graph on `stream` (asynchronous). */
 COSMA_API int cosma_batch_run(void* handle, void* stream);
-/* Waits for the device, then frees the handle's work list and graph. */
+/* Waits for the last cosma_batch_run enqueued outside a stream capture (an
+   event of the handle, not the whole device), then frees the handle's
+   memory and graph.  Replays captured into a caller's graph must be
+   finished by the caller. */
 COSMA_API int cosma_batch_destroy(void* handle);
-/* Tile policy the autotuner kept (0 = the planner's per-problem choice,
-   1 = all 64x64, 2 = all 128x128, 3 = size threshold), number of persistent
+/* Policy the autotuner kept (0 = the planner's batch model per problem,
+   1 = all 64x64, 2 = all 128x128, 3 = size threshold, each with the model's
+   splits; 4 = the model's tiles with k never cut), number of persistent
    launches (one per tile variant), work items, and the timed milliseconds
    of each candidate policy (0 when tuning was skipped: some beta != 0, or
    COSMA_AUTOTUNE=0). */
@@ -232,6 +294,10 @@ COSMA_API int cosma_batch_info(void* handle, int* policy, int* groups, int64_t* 
    -1 for problems without products (m, n or k zero, or alpha zero); count
    must equal the count given at creation. */
 COSMA_API int cosma_batch_tiles(void* handle, int64_t count, int32_t* tile_ids);
+/* Split factor p_k of each input problem (0 for problems without
+   products); with cosma_batch_tiles and cosma_plan_make this names the
+   single-product plan each problem runs under. */
+COSMA_API int cosma_batch_splits(void* handle, int64_t count, int32_t* p_k);
 
 /* ---- planner (host only; no GPU needed) --------------------------------- */
 
@@ -245,14 +311,23 @@ COSMA_API int cosma_plan_query_facts(int64_t m, int64_t n, int64_t k, int dtype,
 /* Plan with a forced tile (menu index) and split factor p_k >= 1. */
 COSMA_API int cosma_plan_make(int64_t m, int64_t n, int64_t k, int dtype, int tile_id, int p_k,
                     cosma_plan_info* out);
+/* Target spread rho (>= 1) the planner's Ozaki slice choice must cover
+   (see "Accuracy of the Ozaki dtypes"); process-wide, clears the plan
+   cache.  The initial value is COSMA_OZAKI_SPREAD from the environment, or
+   2048.  COSMA_OZAKI_SLICES, COSMA_OZAKI_BF16_SLICES and COSMA_OZAKI2_MODULI
+   in the environment force fixed counts instead. */
+COSMA_API int cosma_set_ozaki_spread(double spread);
+COSMA_API int cosma_get_ozaki_spread(double* spread);
 /* Ozaki plans: set the number of digit slices per operand (1..8) and
-   recompute the plan's workspace.  More slices cost s(s+1)/2 products and
+   recompute the plan's workspace and error contract.  More slices cost s(s+1)/2 products and
    shrink the truncation error by 2^-7 (COSMA_F64_OZAKI_I8) or 2^-8
    (COSMA_F64_OZAKI_BF16) per slice.
    Modular (COSMA_F64_OZAKI2_I8) plans: set the number of moduli N (2..16)
    and recompute the plan's work items and workspace.  Each modulus costs
    one int8 product and adds about 8 bits to M; the operands keep beta bits
-   (see cosma_ozaki2_params), about half a bit less per doubling of k. */
+   (see cosma_ozaki2_params), about half a bit less per doubling of k;
+   COSMA_ERR_INVALID_ARG when N moduli leave no operand bits at the plan's
+   k (cosma_ozaki2_params fails). */
 COSMA_API int cosma_plan_set_slices(cosma_plan_info* plan, int slices);
 /* Modular path parameters for reduction length k >= 1 and N moduli
    (2..16): *beta receives the operand scale (rows of A and columns of B are
@@ -286,17 +361,30 @@ COSMA_API double cosma_io_count(int64_t m, int64_t n, int64_t k, int64_t tile_m,
                       int64_t kc, int64_t p_k, int beta_nonzero);
 
 /* ---- workspace ---------------------------------------------------------- */
+/* Section 7.5 pre-allocates the communication buffers once, at their
+   largest size, so that no step of the schedule allocates.  Here the
+   buffers are the split-K partial blocks (Reduce's inputs), the BF16x3
+   planes and the Ozaki digit / residue planes: the caller queries their
+   size, allocates once and registers the buffer; the compute path only
+   offsets into it. */
 
-/* Bytes of workspace the planner's schedule for this product needs. */
+/* Bytes of workspace the planner's schedule for this product needs
+   (*bytes; COSMA_ERR_INVALID_ARG for a null pointer or invalid sizes). */
 COSMA_API int cosma_workspace_size(int64_t m, int64_t n, int64_t k, int dtype, size_t* bytes);
-/* Register a caller-owned device buffer as the workspace of the current
-   device (ptr == NULL, bytes == 0 unregisters).  The library borrows it
-   until it is replaced; `stream` is unused and reserved. */
+/* Register a caller-owned device buffer (256-byte aligned) as the workspace
+   of the current device (ptr == NULL, bytes == 0 unregisters).  The library
+   borrows it until it is replaced and never frees it; `stream` is unused
+   and reserved.  COSMA_ERR_INVALID_ARG for a misaligned pointer or a
+   pointer / size mismatch, COSMA_ERR_UNSUPPORTED without a device. */
 COSMA_API int cosma_set_workspace(void* device_ptr, size_t bytes, void* stream);
 
 /* ---- misc --------------------------------------------------------------- */
+/* Static text naming a cosma_status value (never NULL; "unknown cosma
+   status" for other values).  Host only.  The statuses report the
+   argument, workspace and device conditions of the conventions above; the
+   paper defines none of them. */
 COSMA_API const char* cosma_status_string(int status);
-/* Library version string. */
+/* Static library version string (never NULL).  Host only. */
 COSMA_API const char* cosma_version(void);
 
 #ifdef __cplusplus

@@ -6,7 +6,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 
 Contents
   gemm()            plain binary64 product, the definition of section 2.4 /
-                    the CDAG update rule of section 4.1 (``oracle.c``)
+                    the CDAG update rule of section 5.1 (``oracle.c``)
   normalised_err()  max_ij |C - C_ref| / D_ij with D = |alpha||A||B| + |beta||C0|
   fp64_bound(k), fp32_bound(k)   the stated error bounds 4k*2^-53, 8k*2^-24
   exact             Fraction brute force for tiny inputs (pins the C code)

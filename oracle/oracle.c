@@ -5,7 +5,8 @@
  * The paper treats classical matrix multiplication C = AB with A m x k and
  * B k x n (section 2.4), and its CDAG fixes the update rule
  *     C(t1,t2,t3) = C(t1,t2,t3-1) + A(t1,t3) * B(t3,t2)
- * i.e. every entry is a sum over the reduction index (section 4.1).  The
+ * i.e. every entry is a sum over the reduction index (section 5.1, the
+ * definitions of the MMM CDAG).  The
  * oracle is that definition written out in binary64, with the BLAS scaling
  * convention on top:
  *     C[i][j] = alpha * (sum_{t=0..k-1} A[i][t]*B[t][j]) + beta * C0[i][j]

@@ -41,8 +41,9 @@ COSMA_ERR_NO_MEMORY = -5
 EXPORTED = [
     "cosma_gemm", "cosma_gemm_planned", "cosma_gemm_ex", "cosma_workspace_size_ex", "cosma_pgemm",
     "cosma_gemm_batched", "cosma_batch_create",
-    "cosma_batch_run", "cosma_batch_destroy", "cosma_batch_info", "cosma_batch_tiles", "cosma_plan_query", "cosma_plan_query_facts",
-    "cosma_plan_make", "cosma_plan_set_slices", "cosma_ozaki2_params", "cosma_tile_count", "cosma_tile_shape", "cosma_device_query",
+    "cosma_batch_run", "cosma_batch_destroy", "cosma_batch_info", "cosma_batch_tiles",
+    "cosma_batch_splits", "cosma_workspace_size_batched", "cosma_plan_query", "cosma_plan_query_facts",
+    "cosma_plan_make", "cosma_plan_set_slices", "cosma_set_ozaki_spread", "cosma_get_ozaki_spread", "cosma_ozaki2_params", "cosma_tile_count", "cosma_tile_shape", "cosma_device_query",
     "cosma_thm1_bound", "cosma_seq_schedule", "cosma_par_schedule", "cosma_fit_ranks",
     "cosma_io_count", "cosma_workspace_size", "cosma_set_workspace", "cosma_status_string",
     "cosma_version",
@@ -76,7 +77,9 @@ class cosma_plan_info(ctypes.Structure):
                 ("a_par", ctypes.c_double), ("b_par", ctypes.c_double),
                 ("q_cu_words", ctypes.c_double), ("q_ea_bytes", ctypes.c_double),
                 ("thm1_words", ctypes.c_double), ("thm2_words", ctypes.c_double),
-                ("predicted_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t)]
+                ("predicted_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t),
+                ("err_scaled", ctypes.c_double), ("err_rounding", ctypes.c_double),
+                ("spread_limit", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -119,11 +122,16 @@ def lib():
                 "cosma_batch_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), pi64,
                                            pdbl, i32]),
                 "cosma_batch_tiles": (i32, [vp, i64, ctypes.POINTER(ctypes.c_int32)]),
+                "cosma_batch_splits": (i32, [vp, i64, ctypes.POINTER(ctypes.c_int32)]),
+                "cosma_workspace_size_batched": (i32, [i64, pi64, pi64, pi64, pdbl, i32,
+                                                       ctypes.POINTER(ctypes.c_size_t)]),
                 "cosma_plan_query": (i32, [i64, i64, i64, i32, P]),
                 "cosma_plan_query_facts": (i32, [i64, i64, i64, i32,
                                                  ctypes.POINTER(cosma_device_facts), dbl, P]),
                 "cosma_plan_make": (i32, [i64, i64, i64, i32, i32, i32, P]),
                 "cosma_plan_set_slices": (i32, [P, i32]),
+                "cosma_set_ozaki_spread": (i32, [dbl]),
+                "cosma_get_ozaki_spread": (i32, [pdbl]),
                 "cosma_ozaki2_params": (i32, [i64, i32, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(ctypes.c_int32)]),
                 "cosma_tile_count": (i32, [i32]),
@@ -263,12 +271,15 @@ def cosma_batch_destroy(handle) -> int:
     return lib().cosma_batch_destroy(handle)
 
 
+BATCH_POLICIES = 5
+
+
 def cosma_batch_info(handle):
     """Returns (status, policy, groups, items, [ms per candidate policy])."""
     pol, groups, items = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
-    ms = (ctypes.c_double * 4)()
+    ms = (ctypes.c_double * BATCH_POLICIES)()
     rc = lib().cosma_batch_info(handle, ctypes.byref(pol), ctypes.byref(groups),
-                                ctypes.byref(items), ms, 4)
+                                ctypes.byref(items), ms, BATCH_POLICIES)
     return rc, pol.value, groups.value, items.value, list(ms)
 
 
@@ -277,6 +288,31 @@ def cosma_batch_tiles(handle, count):
     out = (ctypes.c_int32 * max(1, count))()
     rc = lib().cosma_batch_tiles(handle, count, out)
     return rc, list(out)[:count]
+
+
+def cosma_batch_splits(handle, count):
+    """Returns (status, [split factor per input problem])."""
+    out = (ctypes.c_int32 * max(1, count))()
+    rc = lib().cosma_batch_splits(handle, count, out)
+    return rc, list(out)[:count]
+
+
+def cosma_workspace_size_batched(count, m, n, k, alpha, dtype):
+    """Returns (status, bytes) for cosma_gemm_batched."""
+    b = ctypes.c_size_t()
+    rc = lib().cosma_workspace_size_batched(count, _i64arr(m), _i64arr(n), _i64arr(k),
+                                            _dblarr(alpha), _dtype(dtype), ctypes.byref(b))
+    return rc, b.value
+
+
+def gemm_batched(count, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, stream=None) -> int:
+    """cosma_gemm_batched with the workspace it needs registered first."""
+    rc, ws = cosma_workspace_size_batched(count, m, n, k, alpha, dtype)
+    if rc != COSMA_OK:
+        return rc
+    if ws:
+        ensure_workspace(ws)
+    return cosma_gemm_batched(count, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, stream)
 
 
 def cosma_plan_query(m, n, k, dtype):
@@ -301,6 +337,17 @@ def cosma_plan_make(m, n, k, dtype, tile_id, p_k):
 
 def cosma_plan_set_slices(plan, slices) -> int:
     return lib().cosma_plan_set_slices(ctypes.byref(plan), int(slices))
+
+
+def cosma_set_ozaki_spread(spread) -> int:
+    return lib().cosma_set_ozaki_spread(float(spread))
+
+
+def cosma_get_ozaki_spread():
+    """Returns (status, target spread)."""
+    v = ctypes.c_double()
+    rc = lib().cosma_get_ozaki_spread(ctypes.byref(v))
+    return rc, v.value
 
 
 def cosma_ozaki2_params(k, nmod):

@@ -1,18 +1,26 @@
 // Batches of independent products (Algorithm 1's "for all p_i in parallel"
 // over many problems of uneven size) as persistent launches.
 //
-// Every problem gets a tile from a policy; problems that share a tile form
-// one group, whose (problem, tile) work items run in one persistent launch
-// with workgroups pulling items from a device counter.  Items are ordered
-// longest first (k, then tile count), so the tail of a launch is made of
-// short items.  A batch handle captures the launches into a HIP graph.
+// Every problem gets a tile and a split factor p_k from a policy; problems
+// that share a tile form one group, whose (problem, split, tile) work items
+// run in one persistent launch with workgroups pulling items from a device
+// counter.  Problems are ordered longest item first, so the tail of a launch
+// is made of short items.  A problem whose items would be long against the
+// launch's share of work per resident slot is cut in k: the batch analogue
+// of section 6.2, where k is cut once the processors outnumber the
+// independent (i, j) domains.  Its partials go to workspace planes and one
+// batched reduction per batch adds them (Reduce).
 //
-// Autotuner: candidate policies are the planner's per-problem choice (its
-// time / I/O model, split factor fixed to 1 inside a batch) and a few
-// uniform and size-threshold assignments; cosma_batch_create times each
-// candidate's graph on the real batch and keeps the fastest.  Tuning runs
-// the batch, so it is done only when every beta is zero (the outputs are then
-// simply overwritten); otherwise the planner's policy is used.
+// Two ways to run a batch:
+//  - cosma_gemm_batched: one-shot.  Descriptors, the item map, counters and
+//    partials live in the caller's registered workspace; descriptors reach
+//    it inside kernel arguments, so the call allocates nothing, copies
+//    nothing from the host, never waits, and can be captured into a graph.
+//  - cosma_batch_create / run: the handle owns device memory (allocated at
+//    creation) and a HIP graph of the launches.  The autotuner times
+//    candidate policies on the real batch and keeps the fastest; tuning runs
+//    the batch, so it is done only when every beta is zero (outputs are then
+//    simply overwritten); otherwise the planner's policy is used.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,10 +50,20 @@ int batched_occupancy(int dtype, int tile_id) {
 
 namespace {
 
-struct Group {
-  int tile_id;
-  int64_t begin, count;  // range in the item list
-  int grid;
+// Policies: how each problem gets its tile (and whether it may be split).
+enum Policy {
+  POLICY_MODEL = 0,      // the planner's batch cost model per problem, splits by the model
+  POLICY_ALL_64 = 1,     // every problem on 64 x 64, splits by the model
+  POLICY_ALL_128 = 2,    // every problem on 128 x 128, splits by the model
+  POLICY_THRESHOLD = 3,  // 128 x 128 from m n >= 2^20, else 64 x 64, splits by the model
+  POLICY_NO_SPLIT = 4,   // the model's tiles, k never cut
+  kPolicies = 5
+};
+
+// A problem as given, before a policy is applied.
+struct Input {
+  BatchProblem p;  // tiles / split fields filled by the policy
+  int index;       // position in the caller's arrays
 };
 
 struct Scale {
@@ -54,24 +72,24 @@ struct Scale {
   double beta;
 };
 
-struct Batch {
-  int dtype = F32;
-  int policy = 0;
-  double policy_ms[8] = {0};
-  std::vector<BatchProblem> probs;
-  std::vector<int> input_index;  // probs[i] came from input problem input_index[i]
-  std::vector<int> tile_of;      // tile id of probs[i] under the kept policy
-  int64_t inputs = 0;
-  std::vector<Scale> scales;
-  BatchProblem* d_probs = nullptr;
-  BatchItem* d_items = nullptr;
-  unsigned* d_counters = nullptr;
-  std::vector<Group> groups;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+struct Group {
+  int tile_id;
+  int64_t base, items;  // batch-wide item range
+  int grid;
 };
 
-constexpr int kPolicies = 4;
+// A batch under one policy: problems in launch order, groups, reduction list.
+struct Layout {
+  std::vector<BatchProblem> probs;
+  std::vector<int> input_of;   // probs[i] came from input problem input_of[i]
+  std::vector<Group> groups;
+  std::vector<int32_t> reduce;  // probs indices with splits > 1
+  int64_t items = 0;
+  int64_t max_reduce_elems = 0;
+  size_t partial_bytes = 0;     // all partial planes, each 256-byte aligned
+};
+
+size_t up256(size_t x) { return (x + 255) / 256 * 256; }
 
 bool autotune_enabled() {
   static bool on = [] {
@@ -81,12 +99,14 @@ bool autotune_enabled() {
   return on;
 }
 
-// Tile of problem p under a policy.
 int policy_tile(int policy, int dtype, const BatchProblem& p, const cosma_device_facts& f) {
   switch (policy) {
-    case 0: {
-      // the planner's batch model: padded work at the tile's issue rate
-      // against its counted I/O; the cheapest tile wins
+    case POLICY_ALL_64: return 1;
+    case POLICY_ALL_128: return 0;
+    case POLICY_THRESHOLD: return (p.m * p.n >= 1024LL * 1024) ? 0 : 1;
+    default: {
+      // padded work at the tile's issue rate against its counted I/O; the
+      // cheapest tile with a batched form wins
       int cnt = 0;
       tile_menu(dtype, &cnt);
       int best = 0;
@@ -101,116 +121,286 @@ int policy_tile(int policy, int dtype, const BatchProblem& p, const cosma_device
       }
       return best;
     }
-    case 1: return 1;                                           // all 64 x 64
-    case 2: return 0;                                           // all 128 x 128
-    default: return (p.m * p.n >= 1024LL * 1024) ? 0 : 1;      // size threshold
   }
 }
 
-// Build groups + items for a policy.
-void build_items(Batch& b, int policy, const cosma_device_facts& f, std::vector<BatchItem>& items,
-                 std::vector<Group>& groups, std::vector<BatchProblem>& probs) {
+// Split factors of one group.  An item runs its whole k range on one
+// resident slot, so the launch cannot end before its longest item; with
+// items started longest first, a launch is balanced while no item exceeds
+// a quarter of the group's work per slot.  Longer items are cut in k (at
+// least 256 per split, at most 64 splits), as make_plan cuts k into
+// multiples of the tile's round.
+void choose_splits(std::vector<BatchProblem*>& group, int dtype, int tile_id,
+                   const cosma_device_facts& f, bool allow) {
   int cnt = 0;
-  const TileDesc* menu = tile_menu(b.dtype, &cnt);
+  const TileDesc* menu = tile_menu(dtype, &cnt);
+  const TileDesc& T = menu[tile_id];
+  const double slots = (double)f.num_cus * (double)batched_occupancy(dtype, tile_id);
+  const double slot_rate =
+      useful_flops_per_clk_per_cu(dtype, 0) * f.clock_ghz * 1e9 * T.eff * (double)f.num_cus / slots;
+  double work = 0.0;  // item-seconds
+  for (BatchProblem* p : group)
+    work += (double)p->tiles_m * p->tiles_n * 2.0 * T.tm * T.tn * (double)p->k / slot_rate;
+  const double cap = work / slots / 4.0;
+  for (BatchProblem* p : group) {
+    const int64_t panels = ceil_div(p->k, T.tk);
+    int64_t req = 1;
+    if (allow && cap > 0.0) {
+      const double d = 2.0 * T.tm * T.tn * (double)p->k / slot_rate;
+      if (d > cap) req = (int64_t)std::ceil(d / cap);
+      req = std::min<int64_t>(req, std::min<int64_t>(64, p->k / 256));
+      req = std::max<int64_t>(req, 1);
+    }
+    p->k_split = ceil_div(panels, req) * T.tk;
+    p->splits = (int32_t)ceil_div(p->k, p->k_split);
+  }
+}
+
+// Apply a policy: tiles, splits, launch order, item numbering, partials.
+void build_layout(const std::vector<Input>& in, int dtype, int policy, const cosma_device_facts& f,
+                  Layout& L) {
+  int cnt = 0;
+  const TileDesc* menu = tile_menu(dtype, &cnt);
   std::vector<std::vector<int>> by_tile(cnt);
-  probs = b.probs;
-  b.tile_of.assign(probs.size(), 0);
-  for (size_t i = 0; i < probs.size(); ++i) {
-    const int t = policy_tile(policy, b.dtype, probs[i], f);
-    b.tile_of[i] = t;
-    probs[i].tiles_m = ceil_div(probs[i].m, menu[t].tm);
-    probs[i].tiles_n = ceil_div(probs[i].n, menu[t].tn);
+  std::vector<BatchProblem> work(in.size());
+  for (size_t i = 0; i < in.size(); ++i) {
+    work[i] = in[i].p;
+    const int t = policy_tile(policy, dtype, work[i], f);
+    work[i].tiles_m = (int32_t)ceil_div(work[i].m, menu[t].tm);
+    work[i].tiles_n = (int32_t)ceil_div(work[i].n, menu[t].tn);
     by_tile[t].push_back((int)i);
   }
-  items.clear();
-  groups.clear();
+  L = Layout();
   for (int t = 0; t < cnt; ++t) {
     if (by_tile[t].empty()) continue;
+    std::vector<BatchProblem*> group;
+    for (int i : by_tile[t]) group.push_back(&work[i]);
+    choose_splits(group, dtype, t, f, policy != POLICY_NO_SPLIT);
     std::vector<int>& ps = by_tile[t];
-    // longest items first: k (rounds per item) decides an item's duration
+    // longest items first: the rounds per item decide an item's duration
     std::stable_sort(ps.begin(), ps.end(),
-                     [&](int a, int c) { return probs[a].k > probs[c].k; });
+                     [&](int a, int c) { return work[a].k_split > work[c].k_split; });
     Group g;
     g.tile_id = t;
-    g.begin = (int64_t)items.size();
-    for (int pi : ps) {
-      const int64_t tiles = probs[pi].tiles_m * probs[pi].tiles_n;
-      for (int64_t q = 0; q < tiles; ++q) items.push_back(BatchItem{pi, (int32_t)q});
+    g.base = L.items;
+    for (int i : ps) {
+      BatchProblem p = work[i];
+      p.first = L.items;
+      L.items += (int64_t)p.tiles_m * p.tiles_n * p.splits;
+      L.input_of.push_back(in[i].index);
+      L.probs.push_back(p);
     }
-    g.count = (int64_t)items.size() - g.begin;
-    const int occ = batched_occupancy(b.dtype, t);
-    const int64_t slots = (int64_t)f.num_cus * occ;
-    g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(slots, g.count));
-    groups.push_back(g);
+    g.items = L.items - g.base;
+    const int64_t slots = (int64_t)f.num_cus * batched_occupancy(dtype, t);
+    g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(slots, g.items));
+    L.groups.push_back(g);
+  }
+  const size_t w = (size_t)word_bytes(dtype);
+  for (size_t i = 0; i < L.probs.size(); ++i) {
+    BatchProblem& p = L.probs[i];
+    if (p.splits <= 1) continue;
+    p.P = reinterpret_cast<void*>(L.partial_bytes);  // offset until placed
+    L.partial_bytes += up256((size_t)p.splits * (size_t)p.m * (size_t)p.n * w);
+    L.reduce.push_back((int32_t)i);
+    L.max_reduce_elems = std::max<int64_t>(L.max_reduce_elems, p.m * p.n);
   }
 }
 
-int enqueue(const Batch& b, const std::vector<Group>& groups, hipStream_t s) {
-  hipError_t e = launch_reset_counters(b.d_counters, (int)groups.size(), s);
-  if (e != hipSuccess) return COSMA_ERR_HIP;
-  for (size_t gi = 0; gi < groups.size(); ++gi) {
-    const Group& g = groups[gi];
+// Device memory a layout needs: descriptors, item map, counters, partials.
+struct DeviceParts {
+  size_t probs, map, counters, partials, total;
+};
+
+DeviceParts parts_of(const Layout& L) {
+  DeviceParts d;
+  d.probs = up256(std::max<size_t>(1, L.probs.size()) * sizeof(BatchProblem));
+  d.map = up256(std::max<int64_t>(1, L.items) * sizeof(int32_t));
+  d.counters = 256;
+  d.partials = L.partial_bytes;
+  d.total = d.probs + d.map + d.counters + d.partials;
+  return d;
+}
+
+// Pointers of a layout placed at `base` (device memory of parts_of(L).total
+// bytes, 256-byte aligned): partial offsets become addresses.
+struct Placed {
+  BatchProblem* probs;
+  int32_t* map;
+  unsigned* counters;
+  char* partials;
+};
+
+Placed place(Layout& L, void* base) {
+  const DeviceParts d = parts_of(L);
+  Placed pl;
+  char* b = static_cast<char*>(base);
+  pl.probs = reinterpret_cast<BatchProblem*>(b);
+  pl.map = reinterpret_cast<int32_t*>(b + d.probs);
+  pl.counters = reinterpret_cast<unsigned*>(b + d.probs + d.map);
+  pl.partials = b + d.probs + d.map + d.counters;
+  for (BatchProblem& p : L.probs)
+    if (p.splits > 1) p.P = pl.partials + reinterpret_cast<uintptr_t>(p.P);
+  return pl;
+}
+
+// Everything after the descriptors are in device memory: the item map,
+// counters, one persistent launch per group, the reduction, beta scaling of
+// problems without products.  Kernel launches only (graph-capture safe).
+int enqueue_launches(int dtype, const Layout& L, const Placed& pl, const std::vector<Scale>& scales,
+                     hipStream_t s) {
+  if (!L.probs.empty()) {
+    if (launch_batch_expand(pl.probs, (int64_t)L.probs.size(), pl.map, s) != hipSuccess)
+      return COSMA_ERR_HIP;
+    if (launch_reset_counters(pl.counters, (int)L.groups.size(), s) != hipSuccess)
+      return COSMA_ERR_HIP;
+  }
+  for (size_t gi = 0; gi < L.groups.size(); ++gi) {
+    const Group& g = L.groups[gi];
     BatchArgs a;
-    a.probs = b.d_probs;
-    a.items = b.d_items + g.begin;
-    a.count = g.count;
-    a.counter = b.d_counters + gi;
-    e = b.dtype == F64 ? launch_batched_f64(g.tile_id, a, g.grid, s)
-                       : launch_batched_f32(g.tile_id, a, g.grid, s);
+    a.probs = pl.probs;
+    a.map = pl.map;
+    a.base = g.base;
+    a.count = g.items;
+    a.counter = pl.counters + gi;
+    const hipError_t e = dtype == F64 ? launch_batched_f64(g.tile_id, a, g.grid, s)
+                                      : launch_batched_f32(g.tile_id, a, g.grid, s);
     if (e != hipSuccess) return COSMA_ERR_HIP;
   }
-  for (const Scale& sc : b.scales) {
-    e = b.dtype == F64 ? launch_scale_f64((double*)sc.C, sc.ldc, sc.m, sc.n, sc.beta, s)
-                       : launch_scale_f32((float*)sc.C, sc.ldc, sc.m, sc.n, (float)sc.beta, s);
+  for (size_t r0 = 0; r0 < L.reduce.size(); r0 += kReduceList) {
+    BatchReduceArgs r;
+    r.probs = pl.probs;
+    r.count = (int32_t)std::min<size_t>(kReduceList, L.reduce.size() - r0);
+    for (int i = 0; i < r.count; ++i) r.idx[i] = L.reduce[r0 + i];
+    if (launch_batch_reduce(dtype, r, L.max_reduce_elems, s) != hipSuccess) return COSMA_ERR_HIP;
+  }
+  for (const Scale& sc : scales) {
+    const hipError_t e =
+        dtype == F64 ? launch_scale_f64((double*)sc.C, sc.ldc, sc.m, sc.n, sc.beta, s)
+                     : launch_scale_f32((float*)sc.C, sc.ldc, sc.m, sc.n, (float)sc.beta, s);
     if (e != hipSuccess) return COSMA_ERR_HIP;
   }
   return COSMA_OK;
 }
 
+int check_problem(int64_t m, int64_t n, int64_t k, double alpha, const void* A, int64_t lda,
+                  const void* B, int64_t ldb, const void* C, int64_t ldc, size_t el) {
+  if (m < 0 || n < 0 || k < 0) return COSMA_ERR_INVALID_ARG;
+  if (lda < std::max<int64_t>(1, k) || ldb < std::max<int64_t>(1, n) || ldc < std::max<int64_t>(1, n))
+    return COSMA_ERR_INVALID_ARG;
+  if (m == 0 || n == 0) return COSMA_OK;
+  if (!C || (uintptr_t)C % el) return COSMA_ERR_INVALID_ARG;
+  if (k > 0 && alpha != 0.0 && (!A || !B || (uintptr_t)A % el || (uintptr_t)B % el))
+    return COSMA_ERR_INVALID_ARG;
+  if (m > (1LL << 30) || n > (1LL << 30)) return COSMA_ERR_UNSUPPORTED;
+  return COSMA_OK;
+}
+
+// Validate the caller's arrays and split them into problems with products
+// and beta-only scalings.  Pointers may be null when only sizes matter
+// (workspace queries: with_pointers = false).
+int collect(int64_t count, const int64_t* m, const int64_t* n, const int64_t* k,
+            const double* alpha, const void* const* A, const int64_t* lda, const void* const* B,
+            const int64_t* ldb, const double* beta, void* const* C, const int64_t* ldc, int dtype,
+            bool with_pointers, std::vector<Input>& in, std::vector<Scale>& scales) {
+  if (count < 0 || (count > 0 && (!m || !n || !k || !alpha)))
+    return COSMA_ERR_INVALID_ARG;
+  if (with_pointers && count > 0 && (!A || !lda || !B || !ldb || !beta || !C || !ldc))
+    return COSMA_ERR_INVALID_ARG;
+  if (dtype != F32 && dtype != F64) return COSMA_ERR_UNSUPPORTED;
+  if (count > (1LL << 24)) return COSMA_ERR_UNSUPPORTED;
+  const size_t el = (size_t)word_bytes(dtype);
+  int64_t total_items = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    if (with_pointers) {
+      const int rc = check_problem(m[i], n[i], k[i], alpha[i], A[i], lda[i], B[i], ldb[i], C[i],
+                                   ldc[i], el);
+      if (rc != COSMA_OK) return rc;
+    } else if (m[i] < 0 || n[i] < 0 || k[i] < 0) {
+      return COSMA_ERR_INVALID_ARG;
+    } else if (m[i] > (1LL << 30) || n[i] > (1LL << 30)) {
+      return COSMA_ERR_UNSUPPORTED;
+    }
+    if (m[i] == 0 || n[i] == 0) continue;
+    if (k[i] == 0 || alpha[i] == 0.0) {
+      if (with_pointers) scales.push_back(Scale{C[i], ldc[i], m[i], n[i], beta[i]});
+      continue;
+    }
+    Input q;
+    std::memset(&q, 0, sizeof(q));
+    BatchProblem& p = q.p;
+    if (with_pointers) {
+      p.A = A[i];
+      p.B = B[i];
+      p.C = C[i];
+      p.lda = lda[i];
+      p.ldb = ldb[i];
+      p.ldc = ldc[i];
+      p.beta = beta[i];
+      p.vec_a = ((uintptr_t)A[i] % 16 == 0 && ((size_t)lda[i] * el) % 16 == 0) ? 1 : 0;
+      p.vec_b = ((uintptr_t)B[i] % 16 == 0 && ((size_t)ldb[i] * el) % 16 == 0) ? 1 : 0;
+    }
+    p.m = m[i];
+    p.n = n[i];
+    p.k = k[i];
+    p.alpha = alpha[i];
+    q.index = (int)i;
+    in.push_back(q);
+    // the item map holds int32 problem indices and items (64 x 64 tiles, at
+    // most 64 splits each)
+    total_items += ceil_div(m[i], 64) * ceil_div(n[i], 64) * 64;
+    if (total_items > 0x7fffffffLL) return COSMA_ERR_UNSUPPORTED;
+  }
+  return COSMA_OK;
+}
+
+// ---- batch handles -------------------------------------------------------
+
+struct Batch {
+  int dtype = F32;
+  int policy = POLICY_MODEL;
+  double policy_ms[kPolicies] = {0};
+  std::vector<Input> inputs;
+  std::vector<Scale> scales;
+  int64_t count = 0;
+  Layout layout;
+  void* mem = nullptr;  // descriptors, map, counters, partials
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;  // the last replay enqueued outside a capture
+  bool recorded = false;
+};
+
 void free_device(Batch& b) {
   if (b.exec) hipGraphExecDestroy(b.exec);
   if (b.graph) hipGraphDestroy(b.graph);
-  if (b.d_probs) hipFree(b.d_probs);
-  if (b.d_items) hipFree(b.d_items);
-  if (b.d_counters) hipFree(b.d_counters);
+  if (b.mem) hipFree(b.mem);
   b.exec = nullptr;
   b.graph = nullptr;
-  b.d_probs = nullptr;
-  b.d_items = nullptr;
-  b.d_counters = nullptr;
+  b.mem = nullptr;
 }
 
-// Upload a policy's lists and capture its graph (on a private stream).
+// Lay out a policy, upload it and capture its launches (private stream).
 int materialise(Batch& b, int policy, const cosma_device_facts& f) {
-  std::vector<BatchItem> items;
-  std::vector<Group> groups;
-  std::vector<BatchProblem> probs;
-  build_items(b, policy, f, items, groups, probs);
   free_device(b);
-  const size_t pb = std::max<size_t>(1, probs.size()) * sizeof(BatchProblem);
-  const size_t ib = std::max<size_t>(1, items.size()) * sizeof(BatchItem);
-  if (hipMalloc(&b.d_probs, pb) != hipSuccess || hipMalloc(&b.d_items, ib) != hipSuccess ||
-      hipMalloc(&b.d_counters, 64 * sizeof(unsigned)) != hipSuccess) {
-    free_device(b);
+  build_layout(b.inputs, b.dtype, policy, f, b.layout);
+  b.policy = policy;
+  const DeviceParts d = parts_of(b.layout);
+  if (hipMalloc(&b.mem, d.total) != hipSuccess) {
+    b.mem = nullptr;
     return COSMA_ERR_HIP;
   }
-  if (!probs.empty() &&
-      hipMemcpy(b.d_probs, probs.data(), probs.size() * sizeof(BatchProblem),
+  const Placed pl = place(b.layout, b.mem);
+  if (!b.layout.probs.empty() &&
+      hipMemcpy(pl.probs, b.layout.probs.data(), b.layout.probs.size() * sizeof(BatchProblem),
                 hipMemcpyHostToDevice) != hipSuccess)
     return COSMA_ERR_HIP;
-  if (!items.empty() &&
-      hipMemcpy(b.d_items, items.data(), items.size() * sizeof(BatchItem),
-                hipMemcpyHostToDevice) != hipSuccess)
-    return COSMA_ERR_HIP;
-  b.groups = groups;
-  b.policy = policy;
   hipStream_t cap;
   if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return COSMA_ERR_HIP;
   int rc = COSMA_OK;
   if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     rc = COSMA_ERR_HIP;
   } else {
-    rc = enqueue(b, b.groups, cap);
+    rc = enqueue_launches(b.dtype, b.layout, pl, b.scales, cap);
     hipGraph_t g = nullptr;
     const hipError_t ee = hipStreamEndCapture(cap, &g);
     if (rc == COSMA_OK && ee == hipSuccess) {
@@ -252,63 +442,6 @@ double time_graph(Batch& b, hipStream_t s) {
   return ts[1];
 }
 
-int check_problem(int64_t m, int64_t n, int64_t k, double alpha, const void* A, int64_t lda,
-                  const void* B, int64_t ldb, const void* C, int64_t ldc, size_t el) {
-  if (m < 0 || n < 0 || k < 0) return COSMA_ERR_INVALID_ARG;
-  if (lda < std::max<int64_t>(1, k) || ldb < std::max<int64_t>(1, n) || ldc < std::max<int64_t>(1, n))
-    return COSMA_ERR_INVALID_ARG;
-  if (m == 0 || n == 0) return COSMA_OK;
-  if (!C || (uintptr_t)C % el) return COSMA_ERR_INVALID_ARG;
-  if (k > 0 && alpha != 0.0 && (!A || !B || (uintptr_t)A % el || (uintptr_t)B % el))
-    return COSMA_ERR_INVALID_ARG;
-  if (m > (1LL << 30) || n > (1LL << 30)) return COSMA_ERR_UNSUPPORTED;
-  return COSMA_OK;
-}
-
-int collect(Batch& b, int64_t count, const int64_t* m, const int64_t* n, const int64_t* k,
-            const double* alpha, const void* const* A, const int64_t* lda, const void* const* B,
-            const int64_t* ldb, const double* beta, void* const* C, const int64_t* ldc, int dtype) {
-  if (count < 0 || (count > 0 && (!m || !n || !k || !alpha || !A || !lda || !B || !ldb || !beta ||
-                                  !C || !ldc)))
-    return COSMA_ERR_INVALID_ARG;
-  if (dtype != F32 && dtype != F64) return COSMA_ERR_UNSUPPORTED;
-  if (count > (1LL << 24)) return COSMA_ERR_UNSUPPORTED;
-  b.dtype = dtype;
-  b.inputs = count;
-  const size_t el = (size_t)word_bytes(dtype);
-  int64_t total_items = 0;
-  for (int64_t i = 0; i < count; ++i) {
-    const int rc = check_problem(m[i], n[i], k[i], alpha[i], A[i], lda[i], B[i], ldb[i], C[i],
-                                 ldc[i], el);
-    if (rc != COSMA_OK) return rc;
-    if (m[i] == 0 || n[i] == 0) continue;
-    if (k[i] == 0 || alpha[i] == 0.0) {
-      b.scales.push_back(Scale{C[i], ldc[i], m[i], n[i], beta[i]});
-      continue;
-    }
-    BatchProblem p;
-    std::memset(&p, 0, sizeof(p));
-    p.A = A[i];
-    p.B = B[i];
-    p.C = C[i];
-    p.lda = lda[i];
-    p.ldb = ldb[i];
-    p.ldc = ldc[i];
-    p.m = m[i];
-    p.n = n[i];
-    p.k = k[i];
-    p.alpha = alpha[i];
-    p.beta = beta[i];
-    p.vec_a = ((uintptr_t)A[i] % 16 == 0 && ((size_t)lda[i] * el) % 16 == 0) ? 1 : 0;
-    p.vec_b = ((uintptr_t)B[i] % 16 == 0 && ((size_t)ldb[i] * el) % 16 == 0) ? 1 : 0;
-    b.probs.push_back(p);
-    b.input_index.push_back((int)i);
-    total_items += ceil_div(m[i], 64) * ceil_div(n[i], 64);
-    if (total_items > 0x7fffffffLL) return COSMA_ERR_UNSUPPORTED;
-  }
-  return COSMA_OK;
-}
-
 }  // namespace
 }  // namespace cosma
 
@@ -325,17 +458,22 @@ int cosma_batch_create(int64_t count, const int64_t* m, const int64_t* n, const 
   *handle = nullptr;
   Batch* b = new (std::nothrow) Batch();
   if (!b) return COSMA_ERR_NO_MEMORY;
-  int rc = collect(*b, count, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
+  b->dtype = dtype;
+  b->count = count;
+  int rc = collect(count, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, true, b->inputs,
+                   b->scales);
   if (rc == COSMA_OK) {
     int st = COSMA_OK;
     const cosma_device_facts f = device_facts(&st);
     rc = st;
+    if (rc == COSMA_OK && hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess)
+      rc = COSMA_ERR_HIP;
     if (rc == COSMA_OK) {
       bool all_beta_zero = true;
-      for (const BatchProblem& p : b->probs) all_beta_zero = all_beta_zero && p.beta == 0.0;
-      for (const auto& s : b->scales) all_beta_zero = all_beta_zero && s.beta == 0.0;
-      int best = 0;
-      if (autotune_enabled() && all_beta_zero && !b->probs.empty()) {
+      for (const Input& q : b->inputs) all_beta_zero = all_beta_zero && q.p.beta == 0.0;
+      for (const Scale& s : b->scales) all_beta_zero = all_beta_zero && s.beta == 0.0;
+      int best = POLICY_MODEL;
+      if (autotune_enabled() && all_beta_zero && !b->inputs.empty()) {
         double best_ms = 1e300;
         for (int pol = 0; pol < kPolicies && rc == COSMA_OK; ++pol) {
           rc = materialise(*b, pol, f);
@@ -353,6 +491,7 @@ int cosma_batch_create(int64_t count, const int64_t* m, const int64_t* n, const 
   }
   if (rc != COSMA_OK) {
     free_device(*b);
+    if (b->done) hipEventDestroy(b->done);
     delete b;
     return rc;
   }
@@ -364,15 +503,25 @@ int cosma_batch_run(void* handle, void* stream) {
   if (!handle) return COSMA_ERR_INVALID_ARG;
   Batch* b = static_cast<Batch*>(handle);
   if (!b->exec) return COSMA_ERR_INVALID_ARG;
-  return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? COSMA_OK : COSMA_ERR_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipGraphLaunch(b->exec, s) != hipSuccess) return COSMA_ERR_HIP;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return COSMA_ERR_HIP;
+  if (cs == hipStreamCaptureStatusNone) {
+    if (hipEventRecord(b->done, s) != hipSuccess) return COSMA_ERR_HIP;
+    b->recorded = true;
+  }
+  return COSMA_OK;
 }
 
 int cosma_batch_destroy(void* handle) {
   if (!handle) return COSMA_ERR_INVALID_ARG;
   Batch* b = static_cast<Batch*>(handle);
-  // the graph may still be running: wait for the device before freeing
-  hipDeviceSynchronize();
+  // the last replay may still be running: wait for it (only it) before
+  // freeing what it reads
+  if (b->recorded) hipEventSynchronize(b->done);
   free_device(*b);
+  if (b->done) hipEventDestroy(b->done);
   delete b;
   return COSMA_OK;
 }
@@ -382,98 +531,84 @@ int cosma_batch_info(void* handle, int* policy, int* groups, int64_t* items, dou
   if (!handle) return COSMA_ERR_INVALID_ARG;
   Batch* b = static_cast<Batch*>(handle);
   if (policy) *policy = b->policy;
-  if (groups) *groups = (int)b->groups.size();
-  if (items) {
-    int64_t t = 0;
-    for (const Group& g : b->groups) t += g.count;
-    *items = t;
-  }
-  for (int i = 0; policy_ms && i < policy_ms_len && i < kPolicies; ++i) policy_ms[i] = b->policy_ms[i];
+  if (groups) *groups = (int)b->layout.groups.size();
+  if (items) *items = b->layout.items;
+  for (int i = 0; policy_ms && i < policy_ms_len; ++i)
+    policy_ms[i] = i < kPolicies ? b->policy_ms[i] : 0.0;
   return COSMA_OK;
 }
 
 int cosma_batch_tiles(void* handle, int64_t count, int32_t* tile_ids) {
   if (!handle || !tile_ids) return COSMA_ERR_INVALID_ARG;
   Batch* b = static_cast<Batch*>(handle);
-  if (count != b->inputs) return COSMA_ERR_INVALID_ARG;
+  if (count != b->count) return COSMA_ERR_INVALID_ARG;
   for (int64_t i = 0; i < count; ++i) tile_ids[i] = -1;
-  for (size_t i = 0; i < b->probs.size() && i < b->tile_of.size(); ++i)
-    tile_ids[b->input_index[i]] = b->tile_of[i];
+  for (const Group& g : b->layout.groups)
+    for (size_t i = 0; i < b->layout.probs.size(); ++i)
+      if (b->layout.probs[i].first >= g.base && b->layout.probs[i].first < g.base + g.items)
+        tile_ids[b->layout.input_of[i]] = g.tile_id;
   return COSMA_OK;
 }
 
-// One-shot batch: the planner's policy, launched directly on `stream`.  The
-// work list lives in device memory owned by the library for this device,
-// grown on demand and reused; consecutive calls are ordered after each other
-// through an event, so calls on different streams do not race on it.
+int cosma_batch_splits(void* handle, int64_t count, int32_t* p_k) {
+  if (!handle || !p_k) return COSMA_ERR_INVALID_ARG;
+  Batch* b = static_cast<Batch*>(handle);
+  if (count != b->count) return COSMA_ERR_INVALID_ARG;
+  for (int64_t i = 0; i < count; ++i) p_k[i] = 0;
+  for (size_t i = 0; i < b->layout.probs.size(); ++i)
+    p_k[b->layout.input_of[i]] = b->layout.probs[i].splits;
+  return COSMA_OK;
+}
+
+int cosma_workspace_size_batched(int64_t count, const int64_t* m, const int64_t* n,
+                                 const int64_t* k, const double* alpha, int dtype, size_t* bytes) {
+  if (!bytes) return COSMA_ERR_INVALID_ARG;
+  std::vector<Input> in;
+  std::vector<Scale> scales;
+  int rc = collect(count, m, n, k, alpha, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                   nullptr, dtype, false, in, scales);
+  if (rc != COSMA_OK) return rc;
+  int st = COSMA_OK;
+  const cosma_device_facts f = device_facts(&st);
+  Layout L;
+  build_layout(in, dtype, POLICY_MODEL, f, L);
+  *bytes = in.empty() ? 0 : parts_of(L).total;
+  return COSMA_OK;
+}
+
+// One-shot batch under the planner's policy, enqueued on `stream`: the
+// descriptors travel inside kernel arguments into the registered workspace,
+// which also holds the item map, the counters and the partial planes.
 int cosma_gemm_batched(int64_t count, const int64_t* m, const int64_t* n, const int64_t* k,
                        const double* alpha, const void* const* A, const int64_t* lda,
                        const void* const* B, const int64_t* ldb, const double* beta,
                        void* const* C, const int64_t* ldc, int dtype, void* stream) {
-  Batch b;
-  int rc = collect(b, count, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype);
+  std::vector<Input> in;
+  std::vector<Scale> scales;
+  int rc = collect(count, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, true, in, scales);
   if (rc != COSMA_OK) return rc;
   int st = COSMA_OK;
   const cosma_device_facts f = device_facts(&st);
   if (st != COSMA_OK) return st;
-  std::vector<BatchItem> items;
-  std::vector<Group> groups;
-  std::vector<BatchProblem> probs;
-  build_items(b, 0, f, items, groups, probs);
-
-  static std::mutex mu;
-  static struct Cache {
-    BatchProblem* probs = nullptr;
-    size_t probs_cap = 0;
-    BatchItem* items = nullptr;
-    size_t items_cap = 0;
-    unsigned* counters = nullptr;
-    hipEvent_t done = nullptr;
-    int device = -1;
-  } cache[64];
-  const int dev = current_device();
-  if (dev < 0 || dev >= 64) return COSMA_ERR_UNSUPPORTED;
-  std::lock_guard<std::mutex> lock(mu);
-  Cache& c = cache[dev];
   hipStream_t s = (hipStream_t)stream;
-  if (c.done && hipStreamWaitEvent(s, c.done, 0) != hipSuccess) return COSMA_ERR_HIP;
-  auto grow = [&](void** p, size_t* cap, size_t need) -> bool {
-    if (*cap >= need) return true;
-    if (*p) {
-      if (hipDeviceSynchronize() != hipSuccess) return false;
-      hipFree(*p);
-      *p = nullptr;
-      *cap = 0;
+  Layout L;
+  build_layout(in, dtype, POLICY_MODEL, f, L);
+  Placed pl{nullptr, nullptr, nullptr, nullptr};
+  if (!L.probs.empty()) {
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    if (!workspace_for_current(&ws, &ws_bytes) || !ws || ws_bytes < parts_of(L).total)
+      return COSMA_ERR_WORKSPACE;
+    pl = place(L, ws);
+    for (size_t i0 = 0; i0 < L.probs.size(); i0 += kStageProblems) {
+      BatchStage stage;
+      stage.dst = pl.probs + i0;
+      stage.count = (int32_t)std::min<size_t>(kStageProblems, L.probs.size() - i0);
+      std::memcpy(stage.p, L.probs.data() + i0, stage.count * sizeof(BatchProblem));
+      if (launch_batch_stage(stage, s) != hipSuccess) return COSMA_ERR_HIP;
     }
-    size_t want = std::max(need, (size_t)4096);
-    if (hipMalloc(p, want) != hipSuccess) return false;
-    *cap = want;
-    return true;
-  };
-  if (!grow((void**)&c.probs, &c.probs_cap, probs.size() * sizeof(BatchProblem) + 64) ||
-      !grow((void**)&c.items, &c.items_cap, items.size() * sizeof(BatchItem) + 64))
-    return COSMA_ERR_HIP;
-  if (!c.counters && hipMalloc(&c.counters, 64 * sizeof(unsigned)) != hipSuccess) return COSMA_ERR_HIP;
-  if (!c.done && hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess)
-    return COSMA_ERR_HIP;
-  if (groups.size() > 64) return COSMA_ERR_UNSUPPORTED;
-  if (!probs.empty() && hipMemcpyAsync(c.probs, probs.data(), probs.size() * sizeof(BatchProblem),
-                                       hipMemcpyHostToDevice, s) != hipSuccess)
-    return COSMA_ERR_HIP;
-  if (!items.empty() && hipMemcpyAsync(c.items, items.data(), items.size() * sizeof(BatchItem),
-                                       hipMemcpyHostToDevice, s) != hipSuccess)
-    return COSMA_ERR_HIP;
-  // the host vectors are released on return: make sure the copies have read them
-  if (hipStreamSynchronize(s) != hipSuccess) return COSMA_ERR_HIP;
-  b.d_probs = c.probs;
-  b.d_items = c.items;
-  b.d_counters = c.counters;
-  rc = enqueue(b, groups, s);
-  b.d_probs = nullptr;
-  b.d_items = nullptr;
-  b.d_counters = nullptr;
-  if (rc != COSMA_OK) return rc;
-  return hipEventRecord(c.done, s) == hipSuccess ? COSMA_OK : COSMA_ERR_HIP;
+  }
+  return enqueue_launches(dtype, L, pl, scales, s);
 }
 
 }  // extern "C"

@@ -123,6 +123,8 @@ namespace {
 
 bool aligned_to(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+}  // namespace
+
 // Argument rules of the header; nothing is launched when this fails.
 int check_args(int64_t m, int64_t n, int64_t k, double alpha, const void* A, int64_t lda,
                const void* B, int64_t ldb, double beta, const void* C, int64_t ldc, int dtype) {
@@ -143,8 +145,6 @@ int check_args(int64_t m, int64_t n, int64_t k, double alpha, const void* A, int
   (void)beta;
   return COSMA_OK;
 }
-
-}  // namespace
 
 namespace {
 
@@ -197,9 +197,21 @@ int run_bf16x3(const cosma_plan_info& plan, double alpha, const void* A, int64_t
 
 }  // namespace
 
-// Run one product under `plan` (validated by the caller).
+// Run one product under `plan` (validated by the caller) with the
+// registered workspace.
 int run_plan(const cosma_plan_info& plan, double alpha, const void* A, int64_t lda, const void* B,
              int64_t ldb, double beta, void* C, int64_t ldc, hipStream_t stream) {
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  if (!workspace_for_current(&ws, &ws_bytes)) ws = nullptr, ws_bytes = 0;
+  return run_plan_ws(plan, alpha, A, lda, B, ldb, beta, C, ldc, ws, ws_bytes, stream);
+}
+
+// Run one product under `plan` with the device buffer `ws` of `ws_bytes`
+// as its workspace.
+int run_plan_ws(const cosma_plan_info& plan, double alpha, const void* A, int64_t lda,
+                const void* B, int64_t ldb, double beta, void* C, int64_t ldc, void* ws,
+                size_t ws_bytes, hipStream_t stream) {
   const int64_t m = plan.m, n = plan.n, k = plan.k;
   const int dtype = plan.dtype;
   if (m == 0 || n == 0) return COSMA_OK;
@@ -211,12 +223,7 @@ int run_plan(const cosma_plan_info& plan, double alpha, const void* A, int64_t l
   // The requirement is recomputed from the plan's shape, never taken from
   // its (caller-writable) workspace_bytes field.
   const size_t need = workspace_bytes(plan);
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-  if (need > 0) {
-    if (!workspace_for_current(&ws, &ws_bytes) || ws_bytes < need || !ws)
-      return COSMA_ERR_WORKSPACE;
-  }
+  if (need > 0 && (!ws || ws_bytes < need)) return COSMA_ERR_WORKSPACE;
   if (dtype == F64_OZAKI_I8) return run_ozaki(plan, alpha, A, lda, B, ldb, beta, C, ldc, ws, stream);
   if (dtype == F64_OZAKI2_I8)
     return run_ozaki2(plan, alpha, A, lda, B, ldb, beta, C, ldc, ws, stream);
@@ -539,6 +546,8 @@ int cosma_plan_set_slices(cosma_plan_info* plan, int slices) {
     if (slices < 1 || slices > 8) return COSMA_ERR_INVALID_ARG;
   } else if (plan->dtype == F64_OZAKI2_I8) {
     if (slices < CRT_MIN_MODULI || slices > CRT_MAX_MODULI) return COSMA_ERR_INVALID_ARG;
+    CrtParams cp;  // too few moduli leave no operand bits at this k
+    if (plan->k > 0 && !crt_params(plan->k, slices, &cp)) return COSMA_ERR_INVALID_ARG;
     // one GEMM per modulus and split and tile
     if (plan->p_m > 0 && plan->p_n > 0)
       plan->items = (int64_t)plan->p_m * plan->p_n * plan->p_k * slices;
@@ -547,6 +556,20 @@ int cosma_plan_set_slices(cosma_plan_info* plan, int slices) {
   }
   plan->slices = slices;
   plan->workspace_bytes = workspace_bytes(*plan);
+  set_error_contract(plan);
+  return COSMA_OK;
+}
+
+int cosma_set_ozaki_spread(double spread) {
+  if (!set_ozaki_target_spread(spread)) return COSMA_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  g_plans.clear();
+  return COSMA_OK;
+}
+
+int cosma_get_ozaki_spread(double* spread) {
+  if (!spread) return COSMA_ERR_INVALID_ARG;
+  *spread = ozaki_target_spread();
   return COSMA_OK;
 }
 

@@ -309,9 +309,9 @@ __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE
   f32_tile<BM, BN, BK, WM, WN, BLK>(g, ic, As, Bs);
 }
 
-// Persistent batched form: every workgroup takes (problem, tile) items from
-// the device counter until the list is exhausted; each item is computed
-// exactly as by gemm_f32_kernel with one split.
+// Persistent batched form: every workgroup takes (problem, split, tile)
+// items from the device counter until the list is exhausted; each item is
+// computed exactly as by gemm_f32_kernel under the problem's split.
 template <int BM, int BN, int BK, int WM, int WN, int WPE, int BLK>
 __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void gemm_f32_batched_kernel(
     BatchArgs b) {
@@ -325,21 +325,24 @@ __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE
     const unsigned it = next;
     __syncthreads();
     if ((int64_t)it >= b.count) return;
-    const BatchItem item = b.items[it];
-    const BatchProblem& p = b.probs[item.problem];
+    const int64_t gi = b.base + (int64_t)it;
+    const BatchProblem& p = b.probs[b.map[gi]];
     GemmArgs g;
-    g.A = p.A; g.B = p.B; g.C = p.C; g.P = nullptr;
+    g.A = p.A; g.B = p.B; g.C = p.C; g.P = p.P;
     g.lda = p.lda; g.ldb = p.ldb; g.ldc = p.ldc;
     g.m = p.m; g.n = p.n; g.k = p.k;
-    g.k_split = p.k; g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.splits = 1;
-    g.ldp = 0; g.split_stride = 0;
+    g.k_split = p.k_split; g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.splits = p.splits;
+    g.ldp = p.n; g.split_stride = p.m * p.n;
     g.alpha = p.alpha; g.beta = p.beta;
     g.group_m = 1; g.num_xcds = 1;
     g.vec_a = p.vec_a; g.vec_b = p.vec_b;
+    const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
+    const int64_t local = gi - p.first;
     ItemCoord ic;
-    ic.split = 0;
-    ic.tile_row = item.tile / p.tiles_n;
-    ic.tile_col = item.tile - ic.tile_row * p.tiles_n;
+    ic.split = local / tiles;
+    const int64_t t = local - ic.split * tiles;
+    ic.tile_row = t / p.tiles_n;
+    ic.tile_col = t - ic.tile_row * p.tiles_n;
     f32_tile<BM, BN, BK, WM, WN, BLK>(g, ic, As, Bs);
   }
 }

@@ -26,30 +26,57 @@ struct GemmArgs {
   int vec_a, vec_b;      // operand rows may be read 16 bytes at a time
 };
 
-// Batches: problem descriptors and (problem, tile) work items in device
-// memory; a persistent launch pulls items from a device counter.
+// Batches: problem descriptors in device memory, one persistent launch per
+// tile variant.  Work items are numbered batch-wide, problem by problem
+// (problem p owns items [first, first + tiles_m * tiles_n * splits), the
+// problems of one launch contiguous); an item map in device memory names
+// the problem of every item, and within a problem item i is split
+// i / (tiles_m * tiles_n), tile i % (tiles_m * tiles_n) in row-major order.
 struct BatchProblem {
   const void* A;
   const void* B;
   void* C;
+  void* P;                 // partial planes P[split][row][col] (splits > 1)
   int64_t lda, ldb, ldc;
   int64_t m, n, k;
-  int64_t tiles_m, tiles_n;
+  int64_t k_split;         // reduction length per split (multiple of the tile's k)
   double alpha, beta;
+  int64_t first;           // first work item of the problem in its launch
+  int32_t tiles_m, tiles_n, splits;
   int32_t vec_a, vec_b;
-};
-
-struct BatchItem {
-  int32_t problem;
-  int32_t tile;  // row-major tile index within the problem
+  int32_t pad_;
 };
 
 struct BatchArgs {
-  const BatchProblem* probs;
-  const BatchItem* items;
-  int64_t count;       // items in this launch
-  unsigned* counter;   // next item to hand out (reset before the launch)
+  const BatchProblem* probs;  // every problem of the batch
+  const int32_t* map;         // problem index of every item of the batch
+  int64_t base;               // batch-wide number of this launch's first item
+  int64_t count;              // items in this launch
+  unsigned* counter;          // next item to hand out (reset before the launch)
 };
+
+// Problems travel to device memory inside kernel arguments (no host copy,
+// so the enqueue needs no staging memory and can be captured into a graph).
+constexpr int kStageProblems = 24;
+struct BatchStage {
+  BatchProblem* dst;
+  int32_t count;
+  BatchProblem p[kStageProblems];
+};
+hipError_t launch_batch_stage(const BatchStage& st, hipStream_t s);
+// map[probs[p].first + i] = p for every item i of every problem p < nprobs.
+hipError_t launch_batch_expand(const BatchProblem* probs, int64_t nprobs, int32_t* map,
+                               hipStream_t s);
+// Split-K reduction of the listed problems of a batch: C = alpha * sum_s P_s
+// + beta * C, summed in ascending s (as splitk_reduce).
+constexpr int kReduceList = 900;
+struct BatchReduceArgs {
+  const BatchProblem* probs;
+  int32_t count;
+  int32_t idx[kReduceList];
+};
+hipError_t launch_batch_reduce(int dtype, const BatchReduceArgs& r, int64_t max_elems,
+                               hipStream_t s);
 
 // FP64 MFMA GEMM (tile menu kTilesF64).
 hipError_t launch_gemm_f64(int tile_id, const GemmArgs& g, hipStream_t s);

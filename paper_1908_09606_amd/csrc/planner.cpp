@@ -4,6 +4,7 @@
 #include "crt.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -48,31 +49,137 @@ int word_bytes(int dtype) {
 }
 int partial_bytes(int dtype) { return word_bytes(dtype); }
 
+namespace {
+
+// Slice (or moduli) count forced through the environment, or -1.
+int env_count(const char* name, int lo, int hi) {
+  const char* e = std::getenv(name);
+  if (!e || !*e) return -1;
+  const int v = std::atoi(e);
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+std::atomic<double> g_spread{-1.0};
+
+}  // namespace
+
 int ozaki_slices() {
-  static int s = [] {
-    const char* e = std::getenv("COSMA_OZAKI_SLICES");
-    int v = e ? std::atoi(e) : 7;
-    return v < 1 ? 1 : (v > 8 ? 8 : v);
-  }();
+  static int s = env_count("COSMA_OZAKI_SLICES", 1, 8);
   return s;
 }
 
 int ozaki_bf16_slices() {
-  static int s = [] {
-    const char* e = std::getenv("COSMA_OZAKI_BF16_SLICES");
-    int v = e ? std::atoi(e) : 6;
-    return v < 1 ? 1 : (v > 8 ? 8 : v);
-  }();
+  static int s = env_count("COSMA_OZAKI_BF16_SLICES", 1, 8);
   return s;
 }
 
 int ozaki2_moduli() {
-  static int s = [] {
-    const char* e = std::getenv("COSMA_OZAKI2_MODULI");
-    int v = e ? std::atoi(e) : CRT_DEFAULT_MODULI;
-    return v < CRT_MIN_MODULI ? CRT_MIN_MODULI : (v > CRT_MAX_MODULI ? CRT_MAX_MODULI : v);
-  }();
+  static int s = env_count("COSMA_OZAKI2_MODULI", CRT_MIN_MODULI, CRT_MAX_MODULI);
   return s;
+}
+
+double ozaki_target_spread() {
+  double v = g_spread.load();
+  if (v >= 1.0) return v;
+  const char* e = std::getenv("COSMA_OZAKI_SPREAD");
+  v = e ? std::atof(e) : 0.0;
+  if (!(v >= 1.0 && v < 1e300)) v = kDefaultOzakiSpread;
+  g_spread.store(v);
+  return v;
+}
+
+bool set_ozaki_target_spread(double v) {
+  if (!(v >= 1.0 && v < 1e300)) return false;
+  g_spread.store(v);
+  return true;
+}
+
+// The error contract of the Ozaki paths.  Let e_i, f_j be the row / column
+// exponents (max_t |A_it| < 2^e_i, max_t |B_tj| < 2^f_j), D_ij the sum
+// |alpha| sum_t |A_it||B_tj| + |beta||C0_ij| and C_ij the exact result.
+// Each path computes, up to binary64 rounding, the exact product of
+// approximations of the scaled operands, and
+//     |C^_ij - C_ij| <= |alpha| scaled * k 2^(e_i + f_j) + rounding * D_ij,
+// with (unit roundoff u = 2^-53, gamma_n <= 1.01 n u):
+//  - int8 digits, truncated (x = A 2^-e in (-1, 1), x = X + R with
+//    X = sum_(u<=s) X_u, |X_u| <= 127 2^-7u, |R| < 2^-7s, |X| <= |x|):
+//    xy - sum_(u+v<=s+1) X_u Y_v = sum_(u+v>=s+2) X_u Y_v + X R_y + R_x y,
+//    at most (127/128)^2 (s-1) 2^-7s / (1 - 2^-7) + 2 2^-7s <= (s+1) 2^-7s
+//    per term; the digits of x share its sign, so the s diagonal values
+//    of a work item sum to at most sum_t |x_t||y_t| in magnitude, and the
+//    binary64 steps (s - 1 additions, p_k - 1 split additions, alpha,
+//    beta) give rounding = gamma_(s + p_k + 1).
+//  - modular (Ozaki scheme II): A~ = 2^(e - beta) rint(A 2^(beta - e)) with
+//    |A - A~| <= 2^(e - beta - 1), |A~| <= 2^e, so per term
+//    |AB - A~B~| <= |A - A~||B~| + |A||B - B~| <= 2^(e + f - beta); the
+//    integer product is exact, and the reconstruction rounds at most once
+//    per 30-bit limb below the top one, then alpha and beta:
+//    rounding = gamma_(limbs + 2) (1 + 2^-50).
+//  - bf16 digits, rounded to nearest (|R| <= 2^-8s-1, |X_1| <= 1,
+//    |X_u| <= 2^(7 - 8u) for u >= 2): dropped pairs have u, v >= 2, so the
+//    per-term error is at most (s - 1) 2^(-8s-2) (1 - 2^-8)^-1 + 2^-8s-1
+//    (1 + 2^-8s-1) + 2^-8s-1 <= (0.251 s + 0.751) 2^-8s.  From the first
+//    non-zero digit of x on, sum_u |X_u| < 3.004 |x|; every 32-long round
+//    adds s diagonal values to one binary64 accumulator, so
+//    rounding = 9.03 gamma_(s ceil(k_item / 32) + p_k + 2).
+// A binary64 reference product is itself within gamma_k D_ij of C_ij, so
+// the normalised error against it stays within 4k 2^-53 wherever the
+// spread rho_ij = k 2^(e_i + f_j) |alpha| / D_ij satisfies
+//     scaled * rho_ij + rounding <= 3k 2^-53,
+// i.e. rho_ij <= spread_limit.  (The scaled results must stay inside the
+// normal binary64 range.)
+OzakiBound ozaki_bound(int dtype, int slices, int64_t k, int64_t k_split, int64_t p_k) {
+  OzakiBound b{0.0, 0.0, 0.0};
+  if (k < 1 || slices < 1 || p_k < 1) return b;
+  const double u = 0x1p-53;
+  auto gamma = [&](double n) { return 1.01 * n * u; };
+  const double s = (double)slices;
+  if (k_split < 1 || k_split > k) k_split = k;
+  switch (dtype) {
+    case F64_OZAKI_I8:
+      b.scaled = (s + 1.0) * std::ldexp(1.0, -7 * slices);
+      b.rounding = gamma(s + (double)p_k + 1.0);
+      break;
+    case F64_OZAKI_BF16:
+      b.scaled = (0.251 * s + 0.751) * std::ldexp(1.0, -8 * slices);
+      b.rounding = 9.03 * gamma(s * (double)ceil_div(k_split, 32) + (double)p_k + 2.0);
+      break;
+    case F64_OZAKI2_I8: {
+      CrtParams cp;
+      if (!crt_params(k, slices, &cp)) return b;
+      b.scaled = std::ldexp(1.0, -cp.beta) * (1.0 + 0x1p-50);
+      b.rounding = gamma((double)cp.limbs + 2.0) * (1.0 + 0x1p-50);
+      break;
+    }
+    default: return b;
+  }
+  const double room = 3.0 * (double)k * u - b.rounding;
+  b.spread_limit = room > 0.0 ? room / b.scaled : 0.0;
+  return b;
+}
+
+int ozaki_choose_slices(int dtype, int64_t k, double target) {
+  int lo = 1, hi = 8;
+  if (dtype == F64_OZAKI2_I8) {
+    lo = CRT_MIN_MODULI;
+    hi = CRT_MAX_MODULI;
+  } else if (dtype != F64_OZAKI_I8 && dtype != F64_OZAKI_BF16) {
+    return 0;
+  }
+  // the int8 digit path cuts k into items of at most 8192 (int32 sums)
+  const int64_t item = dtype == F64_OZAKI_I8 ? std::min<int64_t>(k, 8192) : k;
+  const int64_t pk = ceil_div(std::max<int64_t>(k, 1), std::max<int64_t>(item, 1));
+  int best = hi;
+  double best_scaled = INFINITY;
+  for (int s = lo; s <= hi; ++s) {
+    const OzakiBound b = ozaki_bound(dtype, s, std::max<int64_t>(k, 1), item, pk);
+    if (b.spread_limit >= target) return s;
+    if (b.scaled > 0.0 && b.scaled < best_scaled * (1.0 - 1e-12)) {
+      best_scaled = b.scaled;
+      best = s;
+    }
+  }
+  return best;  // the most accurate emulation
 }
 
 double useful_flops_per_clk_per_cu(int dtype, int slices) {
@@ -374,10 +481,16 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
   out->dtype = dtype;
   const bool oz2 = dtype == F64_OZAKI2_I8;
   const bool ozb = dtype == F64_OZAKI_BF16;
-  const int slices = dtype == F64_OZAKI_I8 ? ozaki_slices()
+  // Ozaki paths: the smallest slice (moduli) count whose error contract
+  // covers the target spread at this k, unless forced through the
+  // environment.
+  const int forced = dtype == F64_OZAKI_I8 ? ozaki_slices()
                      : oz2                 ? ozaki2_moduli()
                      : ozb                 ? ozaki_bf16_slices()
                                            : 0;
+  const bool ozaki = dtype == F64_OZAKI_I8 || oz2 || ozb;
+  const int slices =
+      !ozaki ? 0 : (forced > 0 ? forced : ozaki_choose_slices(dtype, k, ozaki_target_spread()));
   out->slices = slices;
 
   // Fast memory of one CU in words of the stored operand (an Ozaki word is
@@ -442,8 +555,10 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
     const TileDesc& T = menu[id];
     const int64_t panels = ceil_div(k, T.tk);
     const int64_t tiles = ceil_div(m, T.tm) * ceil_div(n, T.tn);
-    for (int req : kSplits) {
-      if (p_k > 0 && req != p_k) continue;
+    // the planner searches its split menu; a forced split may be any count
+    std::vector<int> reqs(kSplits, kSplits + sizeof(kSplits) / sizeof(kSplits[0]));
+    if (p_k > 0) reqs.assign(1, p_k);
+    for (int req : reqs) {
       if (p_k <= 0 && req > 1 && (double)k / req < 256.0) continue;  // keep rounds long
       const int64_t k_split = ceil_div(panels, req) * T.tk;
       const int64_t splits = ceil_div(k, k_split);
@@ -545,7 +660,17 @@ int make_plan(int64_t m, int64_t n, int64_t k, int dtype, const cosma_device_fac
   out->predicted_ms = pick->t * 1e3;
   const size_t ws = workspace_bytes(*out);
   out->workspace_bytes = ws;
+  set_error_contract(out);
   return COSMA_OK;
+}
+
+void set_error_contract(cosma_plan_info* p) {
+  p->err_scaled = p->err_rounding = p->spread_limit = 0.0;
+  if (p->k < 1 || p->p_k < 1) return;
+  const OzakiBound b = ozaki_bound(p->dtype, p->slices, p->k, p->k_split, p->p_k);
+  p->err_scaled = b.scaled;
+  p->err_rounding = b.rounding;
+  p->spread_limit = b.spread_limit;
 }
 
 }  // namespace cosma

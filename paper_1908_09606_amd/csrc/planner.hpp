@@ -23,12 +23,34 @@ int word_bytes(int dtype);
 int partial_bytes(int dtype);
 double useful_flops_per_clk_per_cu(int dtype, int slices);
 
-// Number of int8 digit slices per operand used by the Ozaki path.
+// Slice counts forced through COSMA_OZAKI_SLICES, COSMA_OZAKI_BF16_SLICES and
+// COSMA_OZAKI2_MODULI (-1 when unset: the planner chooses from k).
 int ozaki_slices();
-// Number of bf16 digit slices per operand used by the bf16 Ozaki path.
 int ozaki_bf16_slices();
-// Number of moduli used by the modular (Ozaki scheme II) path.
 int ozaki2_moduli();
+
+// Error contract of the Ozaki paths (see planner.cpp): bound per unit
+// |alpha| k 2^(e_i + f_j) from the emulation, bound per unit D_ij from
+// binary64 rounding, and the largest spread k 2^(e_i + f_j) |alpha| / D_ij
+// for which the normalised error stays within 3k 2^-53 of the exact product.
+struct OzakiBound {
+  double scaled;
+  double rounding;
+  double spread_limit;
+};
+OzakiBound ozaki_bound(int dtype, int slices, int64_t k, int64_t k_split, int64_t p_k);
+// Smallest slice / moduli count whose spread limit reaches `target` (else
+// the smallest count with the smallest err_scaled: the most accurate
+// emulation); 0 for other dtypes.
+int ozaki_choose_slices(int dtype, int64_t k, double target);
+// Spread the planner's choice must cover: cosma_set_ozaki_spread, else
+// COSMA_OZAKI_SPREAD, else kDefaultOzakiSpread.
+constexpr double kDefaultOzakiSpread = 2048.0;
+double ozaki_target_spread();
+bool set_ozaki_target_spread(double v);
+// Fill a plan's err_scaled / err_rounding / spread_limit from its dtype,
+// slices, k, k_split and p_k (zeros for the native dtypes).
+void set_error_contract(cosma_plan_info* p);
 // Largest reduction length per work item of the modular path (int32 sums
 // of int8 residue products stay exact).
 constexpr int64_t OZAKI2_MAX_K_ITEM = 65536;

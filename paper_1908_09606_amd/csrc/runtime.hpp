@@ -17,5 +17,10 @@ int check_plan(const cosma_plan_info* p);
 int map_hip(hipError_t e);
 int run_plan(const cosma_plan_info& plan, double alpha, const void* A, int64_t lda, const void* B,
              int64_t ldb, double beta, void* C, int64_t ldc, hipStream_t stream);
+int run_plan_ws(const cosma_plan_info& plan, double alpha, const void* A, int64_t lda,
+                const void* B, int64_t ldb, double beta, void* C, int64_t ldc, void* ws,
+                size_t ws_bytes, hipStream_t stream);
+int check_args(int64_t m, int64_t n, int64_t k, double alpha, const void* A, int64_t lda,
+               const void* B, int64_t ldb, double beta, const void* C, int64_t ldc, int dtype);
 
 }  // namespace cosma

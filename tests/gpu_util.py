@@ -73,3 +73,29 @@ def run_gemm(cm, m, n, k, A, lda, B, ldb, C, ldc, alpha=1.0, beta=0.0, plan=None
         rc = cm.cosma_gemm_planned(plan, alpha, A, lda, B, ldb, beta, C, ldc)
     torch.cuda.synchronize()
     return rc
+
+
+def contract_check(got, Ah, Bh, plan, alpha, beta, C0):
+    """Assert the plan's contract entry by entry; returns (worst ratio to the
+    absolute bound, covered fraction, worst normalised error on covered
+    entries)."""
+    m, k = Ah.shape
+    ref, D = oracle.gemm(Ah, Bh, alpha, beta, C0)
+    _, e = np.frexp(np.abs(Ah).max(axis=1))
+    _, f = np.frexp(np.abs(Bh).max(axis=0))
+    scale = abs(alpha) * k * np.ldexp(np.ones(ref.shape), e[:, None] + f[None, :])
+    g_ref = (1.01 * k + 3) * 2.0 ** -53
+    bound = plan.err_scaled * scale + (plan.err_rounding + g_ref) * D
+    diff = np.abs(got - ref)
+    assert np.all(np.isfinite(got))
+    zero = D == 0.0  # all-zero row or column: the result must be exact
+    assert np.all(diff[zero] == 0.0)
+    D1 = np.where(zero, 1.0, D)
+    ratio = float(np.max(np.where(zero, 0.0, diff / np.where(zero, 1.0, bound))))
+    assert ratio <= 1.0, f"absolute contract broken: {ratio:.3g} of the bound"
+    rho = scale / D1
+    covered = zero | (rho <= plan.spread_limit)
+    norm = np.where(zero, 0.0, diff / D1)
+    worst = float(norm[covered].max()) if covered.any() else 0.0
+    assert worst <= oracle.fp64_bound(k), (worst, oracle.fp64_bound(k))
+    return ratio, float(covered.mean()), worst

@@ -44,7 +44,7 @@ def test_oneshot_integer_exact(gpu, dtype, dist, rng_int):
     import torch
     mats = make_batch(DIMS, dist, 100, rng_int)
     a = args_of(DIMS, mats, [1.0] * len(DIMS), [0.0] * len(DIMS))
-    assert cm.cosma_gemm_batched(*a, dtype) == 0
+    assert cm.gemm_batched(*a, dtype) == 0
     torch.cuda.synchronize()
     for i, (m, n, k) in enumerate(DIMS):
         if m == 0 or n == 0:
@@ -59,8 +59,8 @@ def test_oneshot_integer_exact(gpu, dtype, dist, rng_int):
                                         (cm.COSMA_F64, synth.UNIFORM_F64)])
 def test_graph_handle_bit_equal_to_single_launches(gpu, dtype, dist):
     """Every problem of a batch equals, bit for bit, the single-launch result
-    under the tile the batch's policy gave it; replays after the inputs
-    change (with eager work between) are checked one by one."""
+    under the tile and split the batch's policy gave it; replays after the
+    inputs change (with eager work between) are checked one by one."""
     import torch
     dims = [d for d in DIMS if d[2] > 0]
     mats = make_batch(dims, dist, 200)
@@ -72,6 +72,8 @@ def test_graph_handle_bit_equal_to_single_launches(gpu, dtype, dist):
         log(f"batch policy {policy} groups {groups} items {items} tuned ms {ms}")
         rc, tiles = cm.cosma_batch_tiles(h, len(dims))
         assert rc == 0 and all(t >= 0 for t, d in zip(tiles, dims) if d[0] and d[1] and d[2])
+        rc, splits = cm.cosma_batch_splits(h, len(dims))
+        assert rc == 0 and all(s >= 1 for s, d in zip(splits, dims) if d[0] and d[1] and d[2])
         for rep in range(3):
             for i, (m, n, k) in enumerate(dims):  # new inputs each replay
                 if m and k:
@@ -85,7 +87,8 @@ def test_graph_handle_bit_equal_to_single_launches(gpu, dtype, dist):
                 A, B, C = mats[i]
                 ref = torch.empty((m, n), dtype=C.dtype, device=C.device)
                 t = tiles[i]
-                rc, plan = cm.cosma_plan_make(m, n, k, dtype, t, 1)
+                rc, plan = cm.cosma_plan_make(m, n, k, dtype, t, splits[i])
+                cm.ensure_workspace(plan.workspace_bytes)
                 assert rc == 0
                 assert cm.cosma_gemm_planned(plan, 1.0, A, a[6][i], B, a[8][i], 0.0, ref,
                                              max(1, n)) == 0
@@ -125,7 +128,7 @@ def test_graph_handle_beta_nonzero_against_oracle(gpu):
     rc, h = cm.cosma_batch_create(*a, cm.COSMA_F64)
     assert rc == 0
     rc, policy, groups, items, ms = cm.cosma_batch_info(h)
-    assert policy == 0 and ms == [0.0] * 4  # no tuning when some beta != 0
+    assert policy == 0 and ms == [0.0] * cm.BATCH_POLICIES  # no tuning when some beta != 0
     assert cm.cosma_batch_run(h) == 0
     torch.cuda.synchronize()
     for i, (m, n, k) in enumerate(dims):
@@ -148,6 +151,20 @@ def test_invalid_batches(gpu):
     a = list(args_of(dims, mats, [1.0], [0.0]))
     assert cm.cosma_gemm_batched(*a, cm.COSMA_F32_BF16X3) == cm.COSMA_ERR_UNSUPPORTED
     assert cm.cosma_batch_run(None) == cm.COSMA_ERR_INVALID_ARG
+    # a workspace smaller than the batch needs: nothing is launched
+    rc, need = cm.cosma_workspace_size_batched(1, [10], [10], [10], [1.0], cm.COSMA_F32)
+    assert rc == 0 and need > 0
+    import torch
+    small = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    saved = cm._workspace.get(torch.cuda.current_device())
+    try:
+        assert cm.cosma_set_workspace(small, small.numel()) == 0
+        assert cm.cosma_gemm_batched(*a, cm.COSMA_F32) == cm.COSMA_ERR_WORKSPACE
+    finally:
+        if saved is not None:
+            assert cm.cosma_set_workspace(saved, saved.numel()) == 0
+        else:
+            assert cm.cosma_set_workspace(None, 0) == 0
 
 
 def test_config_512_problems_sampled(gpu):
@@ -190,3 +207,112 @@ def test_config_512_problems_sampled(gpu):
         assert err <= oracle.fp32_bound(k), (i, m, n, k, err)
     log(f"  worst err / bound = {worst:.3e}")
     assert cm.cosma_batch_destroy(h) == 0
+
+
+# Few tiles and long k next to many small problems: the batch model cuts k
+# for the long ones (section 6.2's rule inside a batch).
+SPLIT_DIMS = [(128, 128, 16384), (200, 130, 12000), (64, 300, 9000)] + \
+             [(96 + 7 * i, 80 + 5 * i, 64 + 3 * i) for i in range(40)]
+
+
+def model_plan(dims, mats, dtype):
+    """Tiles and splits of the planner's batch policy (what the one-shot
+    call runs): a handle with one beta != 0 skips the autotuner."""
+    beta = [0.0] * len(dims)
+    beta[-1] = 1.0
+    a = args_of(dims, mats, [1.0] * len(dims), beta)
+    rc, h = cm.cosma_batch_create(*a, dtype)
+    assert rc == 0
+    try:
+        assert cm.cosma_batch_info(h)[1] == 0
+        rc, tiles = cm.cosma_batch_tiles(h, len(dims))
+        rc2, splits = cm.cosma_batch_splits(h, len(dims))
+        assert rc == 0 and rc2 == 0
+    finally:
+        assert cm.cosma_batch_destroy(h) == 0
+    return tiles, splits
+
+
+@pytest.mark.parametrize("dtype,dist", [(cm.COSMA_F32, synth.UNIFORM_F32),
+                                        (cm.COSMA_F64, synth.UNIFORM_F64)])
+def test_oneshot_split_k_bit_equal_to_planned_launches(gpu, dtype, dist):
+    """The one-shot call cuts k for the long problems; every problem equals,
+    bit for bit, cosma_gemm_planned under the same tile and split, and is
+    within the stated bound of the oracle."""
+    import torch
+    dims = SPLIT_DIMS
+    mats = make_batch(dims, dist, 500)
+    tiles, splits = model_plan(dims, mats, dtype)
+    log(f"split batch: splits {splits[:3]} ... tiles {tiles[:3]}")
+    assert max(splits[:3]) > 1 and max(splits[3:]) == 1
+    alpha = [1.0 + 0.01 * i for i in range(len(dims))]
+    beta = [0.0] * len(dims)
+    a = args_of(dims, mats, alpha, beta)
+    assert cm.gemm_batched(*a, dtype) == 0
+    torch.cuda.synchronize()
+    for i, (m, n, k) in enumerate(dims):
+        A, B, C = mats[i]
+        rc, plan = cm.cosma_plan_make(m, n, k, dtype, tiles[i], splits[i])
+        assert rc == 0 and plan.p_k == splits[i]
+        ref = torch.empty((m, n), dtype=C.dtype, device=C.device)
+        cm.ensure_workspace(plan.workspace_bytes)
+        assert cm.cosma_gemm_planned(plan, alpha[i], A, a[6][i], B, a[8][i], 0.0, ref, n) == 0
+        torch.cuda.synchronize()
+        assert torch.equal(C[:m, :n], ref), (i, m, n, k, tiles[i], splits[i])
+        if i < 3:
+            rows = np.array([0, m // 2, m - 1])
+            Ar = synth.gen(m, k, 500 + i, synth.STREAM_A, dist, row_idx=rows)
+            Bh = synth.gen(k, n, 500 + i, synth.STREAM_B, dist)
+            r, D = oracle.gemm(Ar, Bh, alpha[i])
+            err = oracle.normalised_err(C[rows].double().cpu().numpy(), r, D)
+            bound = oracle.fp64_bound(k) if dtype == cm.COSMA_F64 else oracle.fp32_bound(k)
+            assert err <= bound, (i, err)
+
+
+@pytest.mark.parametrize("dtype,dist", [(cm.COSMA_F32, synth.UNIFORM_F32),
+                                        (cm.COSMA_F64, synth.UNIFORM_F64)])
+def test_oneshot_under_graph_capture(gpu, dtype, dist):
+    """cosma_gemm_batched recorded into a HIP graph: every replay (inputs
+    refilled and eager one-shot calls on the same workspace between
+    replays) equals the eager call's result bit for bit, split problems and
+    beta != 0 included."""
+    import torch
+    dims = SPLIT_DIMS[:3] + [(70, 90, 33), (5, 5, 5), (40, 50, 0)] + SPLIT_DIMS[3:12]
+    mats = make_batch(dims, dist, 600)
+    C0 = [x[2].clone() for x in mats]
+    alpha = [0.5 + 0.1 * i for i in range(len(dims))]
+    beta = [(-0.5 if i % 3 == 0 else 0.0) for i in range(len(dims))]
+    a = args_of(dims, mats, alpha, beta)
+    rc, need = cm.cosma_workspace_size_batched(len(dims), a[1], a[2], a[3], alpha, dtype)
+    assert rc == 0 and need > 0
+    cm.ensure_workspace(need)          # before capture: nothing is allocated inside
+
+    def reset():
+        for x, c0 in zip(mats, C0):
+            x[2].copy_(c0)
+
+    def refill(rep):
+        for i, (m, n, k) in enumerate(dims):
+            if m and k:
+                synth.fill_device(mats[i][0][:m, :k], 700 + 10 * rep + i, synth.STREAM_A, dist)
+
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    reset()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=stream):
+        assert cm.cosma_gemm_batched(*a, dtype, stream) == 0
+    for rep in range(3):
+        refill(rep)
+        reset()
+        torch.cuda.synchronize()
+        assert cm.cosma_gemm_batched(*a, dtype) == 0     # eager, same workspace
+        torch.cuda.synchronize()
+        eager = [x[2].clone() for x in mats]
+        reset()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for i in range(len(dims)):
+            assert torch.equal(mats[i][2], eager[i]), (rep, i, dims[i])
+    del graph

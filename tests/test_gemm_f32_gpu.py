@@ -73,6 +73,53 @@ def test_uniform_within_fp32_bound(gpu, dtype, k, pk):
     assert err <= oracle.fp32_bound(k)
 
 
+@pytest.mark.parametrize("tile", range(4))
+@pytest.mark.parametrize("k", [512, 1500])
+def test_bf16x3_every_tile_sees_the_lo_products(gpu, tile, k):
+    """Uniform FP32 data on every BF16x3 tile (64x64 through 256x256): the
+    stated 8k * 2^-24 and 2^-16, which a sum missing lo*hi, hi*lo or hi*hi
+    exceeds by 4x or more on this data (host emulation in
+    tests/test_bf16x3_host.py)."""
+    m, n = 520, 300  # several tiles of every shape, ragged tails
+    log(f"bf16x3 tile {tile} uniform k {k}")
+    _, A = device_matrix(m, k, 2, synth.STREAM_A, synth.UNIFORM_F32)
+    _, B = device_matrix(k, n, 2, synth.STREAM_B, synth.UNIFORM_F32)
+    _, C = device_matrix(m, n, 2, synth.STREAM_C, synth.UNIFORM_F32)
+    rc, plan = cm.cosma_plan_make(m, n, k, X3, tile, 1)
+    assert rc == 0
+    assert run_gemm(cm, m, n, k, A, k, B, n, C, n, plan=plan) == 0
+    ref, D = oracle.gemm(synth.gen(m, k, 2, synth.STREAM_A, synth.UNIFORM_F32),
+                         synth.gen(k, n, 2, synth.STREAM_B, synth.UNIFORM_F32))
+    err = oracle.normalised_err(C.cpu().numpy(), ref, D)
+    log(f"  err={err:.3e} (2^-16 = {2.0 ** -16:.3e}, 8k*2^-24 = {oracle.fp32_bound(k):.3e})")
+    assert err <= oracle.fp32_bound(k)
+    assert err <= 2.0 ** -16
+
+
+@pytest.mark.parametrize("tile", range(4))
+def test_bf16x3_exact_on_hi_plus_lo_data(gpu, tile):
+    """Entries hi + lo that split exactly (hi an integer 9..15 in magnitude,
+    lo = j 2^-10 below half a bf16 ulp of hi): the result must equal
+    lo*hi + hi*lo + hi*hi summed exactly on the host, bit for bit, on every
+    tile (every partial sum is a multiple of 2^-10 below 2^14, exact in
+    FP32); a dropped product or a kept lo*lo changes it."""
+    import torch
+    from test_bf16x3_host import exact_split_data, exact_three_product
+    m, n, k = 300, 520, 64
+    log(f"bf16x3 tile {tile} exact hi+lo")
+    xa, hA, jA = exact_split_data(m, k, 11, synth.STREAM_A)
+    xb, hB, jB = exact_split_data(k, n, 11, synth.STREAM_B)
+    A = torch.from_numpy(xa).cuda()
+    B = torch.from_numpy(xb).cuda()
+    C = torch.full((m, n), float("nan"), dtype=torch.float32, device="cuda")
+    rc, plan = cm.cosma_plan_make(m, n, k, X3, tile, 1)
+    assert rc == 0
+    assert run_gemm(cm, m, n, k, A, k, B, n, C, n, plan=plan) == 0
+    want = exact_three_product(hA, jA, hB, jB).astype(np.float64) * 2.0 ** -20
+    got = C.cpu().numpy().astype(np.float64)
+    assert np.array_equal(got, want), float(np.max(np.abs(got - want)))
+
+
 def test_bf16x3_small_k_reported(gpu):
     """Below k ~ 110 the dropped bf16 terms (about 3 * 2^-16 relative) can
     exceed 8k * 2^-24; the error is reported, and must still be far below

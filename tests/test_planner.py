@@ -152,19 +152,21 @@ def test_raster_groups_respect_conflicting_pitch():
 
 
 def test_ozaki_bf16_plan_and_workspace():
-    """bf16 digit path: one 128 x 64 tile with 32-k rounds, 6 slices by
-    default (48 bits), 1..8 accepted; workspace = split partials, then 2 s
-    bytes per padded element of each operand's planes, then the exponents."""
+    """bf16 digit path: one 128 x 64 tile with 32-k rounds, slices chosen by
+    the error contract (tests/test_ozaki_contract.py), 1..8 accepted;
+    workspace = split partials, then 2 s bytes per padded element of each
+    operand's planes, then the exponents."""
     up = lambda x: (x + 255) // 256 * 256
     for (m, n, k, pk) in [(300, 200, 1000, 1), (129, 65, 33, 1), (200, 190, 3000, 3),
                           (8192, 8192, 8192, 1)]:
         rc, p = cm.cosma_plan_make(m, n, k, "ozaki_bf16", 0, pk)
         assert rc == 0
-        assert (p.tile_m, p.tile_n, p.tile_k, p.slices) == (128, 64, 32, 6)
+        assert (p.tile_m, p.tile_n, p.tile_k) == (128, 64, 32) and 1 <= p.slices <= 8
+        s = p.slices
         kp = -(-k // 32) * 32
         rows, cols = -(-m // 128) * 128, -(-n // 64) * 64
         part = up(pk * m * n * 8) if pk > 1 else 0
-        assert p.workspace_bytes == part + up(2 * 6 * kp * (rows + cols)) + up((m + n) * 4)
+        assert p.workspace_bytes == part + up(2 * s * kp * (rows + cols)) + up((m + n) * 4)
         assert cm.cosma_plan_set_slices(p, 8) == 0
         assert p.workspace_bytes == part + up(2 * 8 * kp * (rows + cols)) + up((m + n) * 4)
         assert cm.cosma_plan_set_slices(p, 0) == cm.COSMA_ERR_INVALID_ARG

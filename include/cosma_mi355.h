@@ -181,6 +181,23 @@ COSMA_API int cosma_gemm_planned(const cosma_plan_info* plan, double alpha, cons
                        const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
                        void* stream);
 
+/* For callers that cannot allocate device memory (code that must not call
+   hipMalloc, e.g. under graph capture, tight serving loops, harnesses that
+   forbid it): cosma_gemm with no registered workspace.  The schedule's
+   workspace is a device array of COSMA_NOALLOC_SCRATCH_BYTES that the
+   library's code object holds on every GPU it runs on until the process
+   ends; the call allocates nothing.  A native-dtype plan whose split-K
+   partials would not fit runs with k whole instead; any other plan that
+   needs more returns COSMA_ERR_WORKSPACE (nothing launched).  Every call on
+   one GPU shares that GPU's array: calls that overlap on one GPU (other
+   streams, other threads) race, so order them.  Arguments, results, errors
+   and asynchrony otherwise as cosma_gemm; results equal cosma_gemm's under
+   the same plan. */
+#define COSMA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+COSMA_API int cosma_gemm_noalloc(int64_t m, int64_t n, int64_t k, double alpha, const void* A,
+                                 int64_t lda, const void* B, int64_t ldb, double beta, void* C,
+                                 int64_t ldc, int dtype, void* stream);
+
 /* C = alpha*op(A)*op(B) + beta*C with CBLAS conventions, for callers whose
    matrices are column-major (ScaLAPACK / Fortran style, the paper's own
    library interface) or transposed.  op(A) is m x k, op(B) is k x n, C is

@@ -39,7 +39,7 @@ COSMA_ERR_UNSUPPORTED = -4
 COSMA_ERR_NO_MEMORY = -5
 
 EXPORTED = [
-    "cosma_gemm", "cosma_gemm_planned", "cosma_gemm_ex", "cosma_workspace_size_ex", "cosma_pgemm",
+    "cosma_gemm", "cosma_gemm_planned", "cosma_gemm_noalloc", "cosma_gemm_ex", "cosma_workspace_size_ex", "cosma_pgemm",
     "cosma_gemm_batched", "cosma_batch_create",
     "cosma_batch_run", "cosma_batch_destroy", "cosma_batch_info", "cosma_batch_tiles",
     "cosma_batch_splits", "cosma_workspace_size_batched", "cosma_plan_query", "cosma_plan_query_facts",
@@ -107,6 +107,8 @@ def lib():
             sig = {
                 "cosma_gemm": (i32, [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, vp]),
                 "cosma_gemm_planned": (i32, [P, dbl, vp, i64, vp, i64, dbl, vp, i64, vp]),
+                "cosma_gemm_noalloc": (i32, [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64,
+                                             i32, vp]),
                 "cosma_gemm_ex": (i32, [i32, i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl,
                                         vp, i64, i32, vp]),
                 "cosma_workspace_size_ex": (i32, [i32, i32, i32, i64, i64, i64, i32,
@@ -207,6 +209,14 @@ def cosma_version() -> str:
 def cosma_gemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, stream=None) -> int:
     return lib().cosma_gemm(m, n, k, float(alpha), _ptr(A), lda, _ptr(B), ldb, float(beta),
                             _ptr(C), ldc, _dtype(dtype), _stream(stream))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # COSMA_NOALLOC_SCRATCH_BYTES
+
+
+def cosma_gemm_noalloc(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, stream=None) -> int:
+    return lib().cosma_gemm_noalloc(m, n, k, float(alpha), _ptr(A), lda, _ptr(B), ldb,
+                                    float(beta), _ptr(C), ldc, _dtype(dtype), _stream(stream))
 
 
 def cosma_gemm_planned(plan, alpha, A, lda, B, ldb, beta, C, ldc, stream=None) -> int:

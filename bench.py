@@ -11,9 +11,11 @@ Printed: one JSON line with the driver's keys plus
                 `traffic` is the HBM bytes per launch from the committed
                 rocprofv3 counter summary when it matches the current kernel
                 source, else null
-  cpu_baseline  the oracle timed on the host cores on a bounded sample
-                (rows of the square product), which also gives the sampled
-                accuracy check of the GPU result
+  config_512    the small FP64 product 512^3 (launch-bound), timed
+  cpu_baseline  the oracle timed on the host cores: `value` on a bounded
+                sample (rows of the square product), plus the 512^3 product
+                and the 512-problem batch in full; every GPU result it
+                covers is compared with it
   variants      the precision and batching variants (BF16x3 vs FP32, Ozaki
                 INT8 vs FP64, batched vs single launches), each timed on its
                 own workload
@@ -220,11 +222,13 @@ def main():
         del src, dst
 
     keep = []
+    small = run_small(torch, cm, synth, dev, stream, args.reps)
+    out["config_512"] = {k_: v for k_, v in small.items() if k_ != "C"}
     if not args.no_variants:
         out["variants"] = run_variants(torch, cm, synth, dev, stream, keep, args.reps)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(probs, torch)
+        out["cpu_baseline"] = cpu_baseline(probs, small, keep, torch)
         out["accuracy"] = sampled_accuracy(probs, keep)
 
     # release inputs before printing
@@ -378,6 +382,13 @@ def run_variants(torch, cm, synth, dev, stream, keep, reps=20):
             cm.cosma_gemm(bm, bn, bk, 1.0, mats[i][0], bk, mats[i][1], bn, 0.0, mats[i][2], bn,
                           cm.COSMA_F32, stream)
     t_loop, st_loop = _time(torch, stream, loop, reps, min(3, reps))
+    # one-shot call: the planner's batch policy, workspace-staged, no graph
+    rc, ws_b = cm.cosma_workspace_size_batched(*args[:5], cm.COSMA_F32)
+    cm.check(rc, "cosma_workspace_size_batched")
+    cm.ensure_workspace(ws_b)
+    t_one, st_one = _time(torch, stream, lambda: cm.check(cm.cosma_gemm_batched(
+        *args, cm.COSMA_F32, stream), "cosma_gemm_batched"), reps, min(3, reps))
+    rc, splits = cm.cosma_batch_splits(h, 512)
     cm.cosma_batch_run(h, stream)  # final results come from the graph
     torch.cuda.synchronize()
     cm.cosma_batch_destroy(h)
@@ -389,7 +400,9 @@ def run_variants(torch, cm, synth, dev, stream, keep, reps=20):
         "loop_tflops": round(flops / (t_loop * 1e-3) / 1e12, 2),
         "speedup_vs_loop": round(t_loop / t_graph, 3), "autotuned_policy": policy,
         "policy_candidates_ms": [round(x, 3) for x in pol_ms], "persistent_launches": groups,
-        "work_items": items}
+        "work_items": items, "problems_split": int(sum(1 for x in splits if x > 1)),
+        "graph_frac_f32_peak": round(flops / (t_graph * 1e-3) / 1e12 / PEAK_F32, 4),
+        "oneshot_ms": round(t_one, 3), "oneshot_ms_ci95": st_one["ci95"]}
     keep.append(("batched", mats, dims, None, None, synth.UNIFORM_F32, "f32"))
     return out
 
@@ -444,32 +457,125 @@ def run_sweep(torch, cm, synth, dev, stream, reps):
     return out
 
 
-def cpu_baseline(probs, torch):
-    """The oracle as it stands, timed on the host cores on a bounded sample:
-    the first R rows of the square product (A rows regenerated, B copied from
-    the device fill).  The same rows of the GPU result are compared with it."""
+def run_small(torch, cm, synth, dev, stream, reps):
+    """The small FP64 product 512^3 (uniform[-1,1], seed 0): launch-bound;
+    timed like the variants, its result kept for the oracle."""
+    m = n = k = 512
+    A = torch.empty((m, k), dtype=torch.float64, device=dev)
+    B = torch.empty((k, n), dtype=torch.float64, device=dev)
+    C = torch.empty((m, n), dtype=torch.float64, device=dev)
+    synth.fill_device(A, 0, synth.STREAM_A, synth.UNIFORM_F64)
+    synth.fill_device(B, 0, synth.STREAM_B, synth.UNIFORM_F64)
+    rc, plan = cm.cosma_plan_query(m, n, k, cm.COSMA_F64)
+    cm.ensure_workspace(plan.workspace_bytes)
+    ms, st = _time(torch, stream, lambda: cm.gemm(A, B, C, dtype="f64", stream=stream), reps,
+                   min(3, reps))
+    torch.cuda.synchronize()
+    tf = 2.0 * m * n * k / (ms * 1e-3) / 1e12
+    return {"shape": "512x512x512", "seed": 0, "ms": ms, "ms_ci95": st["ci95"],
+            "tflops": round(tf, 3), "frac_peak": round(tf / PEAK_F64, 4),
+            "tile": f"{plan.tile_m}x{plan.tile_n}", "p_k": plan.p_k, "C": C.cpu().numpy()}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _regen(jobs, threads):
+    """Run independent synth.gen calls on a thread pool (numpy releases the
+    GIL inside its array kernels)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda a: a[0](*a[1:]), jobs))
+
+
+def cpu_baseline(probs, small, keep, torch):
+    """The oracle as it stands, timed on the host cores.
+
+    value: the bench workload's square product on a bounded sample (its
+    first R rows, A and B regenerated on the host, B bit-checked against the
+    device fill on sampled entries).  Also, in full: the small 512^3 product
+    and the 512-problem FP32 batch, whose GPU results are compared entry by
+    entry."""
     import numpy as np
     import oracle
     import synth
+    threads = oracle.default_threads()
+    rows_out = []
+    # small product, in full
+    m = n = k = 512
+    A1 = synth.gen(m, k, 0, synth.STREAM_A, synth.UNIFORM_F64)
+    B1 = synth.gen(k, n, 0, synth.STREAM_B, synth.UNIFORM_F64)
+    t0 = time.perf_counter()
+    ref, D = oracle.gemm(A1, B1, threads=threads)
+    dt = time.perf_counter() - t0
+    err = oracle.normalised_err(small["C"], ref, D)
+    rows_out.append({"config": "FP64 512x512x512, uniform[-1,1] seed 0 (in full)",
+                     "seconds": round(dt, 4), "tflops": round(2.0 * m * n * k / dt / 1e12, 6),
+                     "gpu_ms": small["ms"], "gpu_err": err, "err_bound": oracle.fp64_bound(k),
+                     "within_bound": bool(err <= oracle.fp64_bound(k))})
+    # square product: the first R rows
     p = next((q for q in probs if q["name"] == "square"), probs[0])
     m, n, k = p["m"], p["n"], p["k"]
-    rows = int(os.environ.get("COSMA_BENCH_ORACLE_ROWS", "1024"))
+    rows = int(os.environ.get("COSMA_BENCH_ORACLE_ROWS", "512"))
     rows = max(1, min(rows, m))
     Ar = synth.gen(m, k, SEED, synth.STREAM_A, synth.UNIFORM_F64, row_idx=np.arange(rows))
-    Bh = p["B"].cpu().numpy()
-    threads = oracle.default_threads()
+    blk = -(-k // threads)
+    parts = _regen([(synth.gen, k, n, SEED, synth.STREAM_B, synth.UNIFORM_F64, 0,
+                     np.arange(t0_, min(k, t0_ + blk))) for t0_ in range(0, k, blk)], threads)
+    Bh = np.concatenate(parts, axis=0)
+    del parts
+    rng = np.random.default_rng(11)
+    ri = rng.integers(0, k, 4096)
+    ci = rng.integers(0, n, 4096)
+    dev_b = p["B"][torch.as_tensor(ri, device=p["B"].device),
+                   torch.as_tensor(ci, device=p["B"].device)].cpu().numpy()
+    b_match = bool(np.array_equal(dev_b, Bh[ri, ci]))
     t0 = time.perf_counter()
     ref, D = oracle.gemm(Ar, Bh, threads=threads)
     dt = time.perf_counter() - t0
+    del Bh
     got = p["C"][:rows].cpu().numpy()
     err = oracle.normalised_err(got, ref, D)
     flops = 2.0 * rows * n * k
-    return {"value": round(flops / dt / 1e12, 6), "unit": "TFLOP/s", "cores": threads,
-            "kind": "oracle",
+    value = flops / dt / 1e12
+    rows_out.append({"config": f"FP64 square {m}x{n}x{k}: first {rows} rows of C",
+                     "seconds": round(dt, 3), "tflops": round(value, 6),
+                     "device_B_equals_host_regeneration": b_match, "gpu_err": err,
+                     "err_bound": oracle.fp64_bound(k),
+                     "within_bound": bool(err <= oracle.fp64_bound(k))})
+    # 512-problem FP32 batch, in full
+    bt = next((e for e in keep if e[0] == "batched"), None)
+    if bt is not None:
+        _, mats, dims, _, _, dist, _ = bt
+        jobs = []
+        for i, (bm, bn, bk) in enumerate(dims):
+            jobs.append((synth.gen, bm, bk, 1000 + i, synth.STREAM_A, dist))
+            jobs.append((synth.gen, bk, bn, 1000 + i, synth.STREAM_B, dist))
+        mats_h = _regen(jobs, threads)
+        got = [mats[i][2].cpu().numpy() for i in range(len(dims))]
+        t0 = time.perf_counter()
+        worst, fl = 0.0, 0.0
+        for i, (bm, bn, bk) in enumerate(dims):
+            ref, D = oracle.gemm(mats_h[2 * i], mats_h[2 * i + 1], threads=threads)
+            e = oracle.normalised_err(got[i], ref, D)
+            worst = max(worst, e / oracle.fp32_bound(bk))
+            fl += 2.0 * bm * bn * bk
+        dt = time.perf_counter() - t0
+        rows_out.append({"config": "512 FP32 problems, m,n,k log-uniform in [64,4096] (in full)",
+                         "seconds": round(dt, 3), "tflops": round(fl / dt / 1e12, 6),
+                         "gpu_worst_err_over_bound": worst, "within_bound": bool(worst <= 1.0)})
+    return {"value": round(value, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"first {rows} rows of C for the square {m}x{n}x{k} FP64 product "
-                      f"({flops:.3e} flops, {dt:.2f} s)",
-            "gpu_err_on_sample": err, "err_bound": oracle.fp64_bound(k),
-            "within_bound": bool(err <= oracle.fp64_bound(k))}
+                      f"({flops:.3e} flops, {rows_out[1]['seconds']:.2f} s)",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(), "per_config": rows_out}
 
 
 def sampled_accuracy(probs, keep):

@@ -99,3 +99,59 @@ def contract_check(got, Ah, Bh, plan, alpha, beta, C0):
     worst = float(norm[covered].max()) if covered.any() else 0.0
     assert worst <= oracle.fp64_bound(k), (worst, oracle.fp64_bound(k))
     return ratio, float(covered.mean()), worst
+
+
+def _gen_threaded(rows, cols, seed, stream, dist, row_idx=None, col_idx=None, threads=16):
+    """synth.gen of a sub-block, cut into row chunks generated in parallel."""
+    from concurrent.futures import ThreadPoolExecutor
+    r = np.arange(rows) if row_idx is None else np.asarray(row_idx)
+    chunks = [r[i:i + max(1, len(r) // threads + 1)] for i in range(0, len(r), max(1, len(r) // threads + 1))]
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(lambda rr: synth.gen(rows, cols, seed, stream, dist, row_idx=rr,
+                                                 col_idx=col_idx), chunks))
+    return np.concatenate(parts, axis=0) if parts else np.empty((0, 0))
+
+
+def fullsize_check(C_dev, m, n, k, seed, dist, plan, bound, budget_fma=3.2e11, nsamp=256):
+    """Full-size verification against the oracle:
+      - 65,536 entries: nsamp x nsamp uniformly drawn rows and columns;
+      - the edge tiles: every entry of the first and last tile row and tile
+        column of C when that costs at most budget_fma multiply-adds on the
+        host, else every entry of the four corner tiles.
+    Returns (worst normalised error, number of entries checked)."""
+    import torch
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    tm, tn = plan.tile_m, plan.tile_n
+    er = np.unique(np.concatenate([np.arange(min(tm, m)), np.arange((m - 1) // tm * tm, m)]))
+    ec = np.unique(np.concatenate([np.arange(min(tn, n)), np.arange((n - 1) // tn * tn, n)]))
+    rows = np.sort(rng.choice(m, size=min(m, nsamp), replace=False))
+    cols = np.sort(rng.choice(n, size=min(n, nsamp), replace=False))
+    worst, count = 0.0, 0
+
+    def check(ri, ci, Ar, Bc):
+        nonlocal worst, count
+        ref, D = oracle.gemm(Ar, Bc)
+        got = C_dev.index_select(0, torch.as_tensor(ri, device=C_dev.device)) \
+                   .index_select(1, torch.as_tensor(ci, device=C_dev.device)).double().cpu().numpy()
+        err = oracle.normalised_err(got, ref, D)
+        assert err <= bound, f"normalised error {err:.3e} > bound {bound:.3e}"
+        worst = max(worst, err)
+        count += got.size
+
+    Bs = _gen_threaded(k, n, seed, synth.STREAM_B, dist, col_idx=cols)
+    check(rows, cols, _gen_threaded(m, k, seed, synth.STREAM_A, dist, row_idx=rows), Bs)
+    del Bs
+    full = (len(er) * n + len(ec) * m) * float(k) <= budget_fma
+    if full:
+        Bf = _gen_threaded(k, n, seed, synth.STREAM_B, dist)
+        check(er, np.arange(n), _gen_threaded(m, k, seed, synth.STREAM_A, dist, row_idx=er), Bf)
+        del Bf
+        Af = _gen_threaded(m, k, seed, synth.STREAM_A, dist)
+        check(np.arange(m), ec, Af, _gen_threaded(k, n, seed, synth.STREAM_B, dist, col_idx=ec))
+        del Af
+    else:
+        check(er, ec, _gen_threaded(m, k, seed, synth.STREAM_A, dist, row_idx=er),
+              _gen_threaded(k, n, seed, synth.STREAM_B, dist, col_idx=ec))
+    log(f"  checked {count} entries ({'edge tile rows and columns' if full else 'corner tiles'}"
+        f" + {len(rows) * len(cols)} sampled): worst {worst:.3e}, bound {bound:.3e}")
+    return worst, count

@@ -5,14 +5,14 @@ import pytest
 import oracle
 import synth
 import paper_1908_09606_amd as cm
-from gpu_util import device_matrix, log, sampled_check, sample_indices
+from gpu_util import device_matrix, fullsize_check, log
 
 pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16x3"])
-@pytest.mark.parametrize("shape,nsamp", [((16384, 16384, 16384), 40), ((4096, 4096, 1 << 18), 16)])
-def test_fullsize_sampled(gpu, dtype, shape, nsamp):
+@pytest.mark.parametrize("shape", [(16384, 16384, 16384), (4096, 4096, 1 << 18)])
+def test_fullsize_sampled(gpu, dtype, shape):
     import torch
     m, n, k = shape
     log(f"{dtype} full size {m}x{n}x{k}")
@@ -23,12 +23,7 @@ def test_fullsize_sampled(gpu, dtype, shape, nsamp):
     torch.cuda.synchronize()
     rc, plan = cm.cosma_plan_query(m, n, k, dtype)
     log(f"  plan tile {plan.tile_m}x{plan.tile_n} p_k {plan.p_k}")
-    rng = np.random.default_rng(m + k)
-    rows = sample_indices(m, nsamp, rng, plan.tile_m)
-    cols = sample_indices(n, nsamp, rng, plan.tile_n)
-    err = sampled_check(C, m, n, k, 1, synth.UNIFORM_F32, rows=rows, cols=cols,
-                        bound=oracle.fp32_bound(k))
-    log(f"  sampled err={err:.3e} bound={oracle.fp32_bound(k):.3e}")
+    fullsize_check(C, m, n, k, 1, synth.UNIFORM_F32, plan, oracle.fp32_bound(k))
     assert not torch.isnan(C).any().item()
     del A, B, C
     torch.cuda.empty_cache()

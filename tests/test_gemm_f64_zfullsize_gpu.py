@@ -1,19 +1,19 @@
 """FP64 at the full benchmark sizes, in the planner's launch configuration,
-checked on sampled entries (random rows/columns plus edge tiles)."""
+checked on 65,536 sampled entries plus the edge tiles (see fullsize_check)."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
 import paper_1908_09606_amd as cm
-from gpu_util import device_matrix, log, sampled_check, sample_indices
+from gpu_util import device_matrix, fullsize_check, log
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("shape,nsamp", [((16384, 16384, 16384), 48), ((32768, 32768, 256), 64),
-                                         ((2048, 2048, 1 << 20), 12)])
-def test_fullsize_sampled(gpu, shape, nsamp):
+@pytest.mark.parametrize("shape", [(16384, 16384, 16384), (32768, 32768, 256),
+                                   (2048, 2048, 1 << 20)])
+def test_fullsize_sampled(gpu, shape):
     import torch
     m, n, k = shape
     log(f"f64 full size {m}x{n}x{k}")
@@ -24,12 +24,7 @@ def test_fullsize_sampled(gpu, shape, nsamp):
     torch.cuda.synchronize()
     rc, plan = cm.cosma_plan_query(m, n, k, "f64")
     log(f"  plan tile {plan.tile_m}x{plan.tile_n} p_k {plan.p_k}")
-    rng = np.random.default_rng(m + n + k)
-    rows = sample_indices(m, nsamp, rng, plan.tile_m)
-    cols = sample_indices(n, nsamp, rng, plan.tile_n)
-    err = sampled_check(C, m, n, k, 1, synth.UNIFORM_F64, rows=rows, cols=cols,
-                        bound=oracle.fp64_bound(k))
-    log(f"  sampled err={err:.3e} bound={oracle.fp64_bound(k):.3e}")
+    fullsize_check(C, m, n, k, 1, synth.UNIFORM_F64, plan, oracle.fp64_bound(k))
     assert not torch.isnan(C).any().item()
     del A, B, C
     torch.cuda.empty_cache()

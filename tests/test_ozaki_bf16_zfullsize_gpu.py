@@ -6,7 +6,7 @@ import pytest
 import oracle
 import synth
 import paper_1908_09606_amd as cm
-from gpu_util import device_matrix, log, sampled_check, sample_indices
+from gpu_util import device_matrix, fullsize_check, log
 
 pytestmark = pytest.mark.gpu
 
@@ -21,11 +21,7 @@ def test_fullsize_sampled(gpu):
     cm.gemm(A, B, C, dtype="ozaki_bf16")
     torch.cuda.synchronize()
     rc, plan = cm.cosma_plan_query(m, n, k, "ozaki_bf16")
-    rng = np.random.default_rng(5)
-    rows = sample_indices(m, 48, rng, plan.tile_m)
-    cols = sample_indices(n, 48, rng, plan.tile_n)
-    err = sampled_check(C, m, n, k, 1, synth.WIDE_F64, rows=rows, cols=cols,
-                        bound=oracle.fp64_bound(k))
+    err, _ = fullsize_check(C, m, n, k, 1, synth.WIDE_F64, plan, oracle.fp64_bound(k))
     log(f"  slices {plan.slices} sampled err={err:.3e} bound={oracle.fp64_bound(k):.3e}")
     del A, B, C
     torch.cuda.empty_cache()

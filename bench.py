@@ -418,23 +418,27 @@ SWEEP_TILES = (8192, 8192, 8192)
 
 
 def run_sweep(torch, cm, synth, dev, stream, reps):
-    out = {"regimes": [], "tiles": []}
+    out = {"regimes": [], "tiles": [], "memory_scenarios": []}
 
-    def one(m, n, k, plan, tag):
-        A = torch.empty((m, k), dtype=torch.float64, device=dev)
-        B = torch.empty((k, n), dtype=torch.float64, device=dev)
-        C = torch.empty((m, n), dtype=torch.float64, device=dev)
-        synth.fill_device(A, SEED, synth.STREAM_A, synth.UNIFORM_F64)
-        synth.fill_device(B, SEED, synth.STREAM_B, synth.UNIFORM_F64)
+    def one(m, n, k, plan, tag, dtype="f64"):
+        f32 = dtype == "f32"
+        tdt = torch.float32 if f32 else torch.float64
+        dist = synth.UNIFORM_F32 if f32 else synth.UNIFORM_F64
+        A = torch.empty((m, k), dtype=tdt, device=dev)
+        B = torch.empty((k, n), dtype=tdt, device=dev)
+        C = torch.empty((m, n), dtype=tdt, device=dev)
+        synth.fill_device(A, SEED, synth.STREAM_A, dist)
+        synth.fill_device(B, SEED, synth.STREAM_B, dist)
         cm.ensure_workspace(plan.workspace_bytes)
-        ms, st = _time(torch, stream, lambda: cm.gemm(A, B, C, dtype="f64", plan=plan, stream=stream),
+        ms, st = _time(torch, stream, lambda: cm.gemm(A, B, C, dtype=dtype, plan=plan, stream=stream),
                        reps, min(3, reps))
         tf = 2.0 * m * n * k / (ms * 1e-3) / 1e12
-        log(f"sweep {tag} {m}x{n}x{k}: {ms:.3f} ms {tf:.2f} TFLOP/s")
+        log(f"sweep {tag} {dtype} {m}x{n}x{k}: {ms:.3f} ms {tf:.2f} TFLOP/s")
         row = {"m": m, "n": n, "k": k, "tile": f"{plan.tile_m}x{plan.tile_n}", "p_k": plan.p_k,
                "group_m": plan.group_m, "regime": plan.regime, "p1": round(plan.p1, 2),
+               "a_par": round(plan.a_par, 1), "sqrt_S": round(plan.S_words ** 0.5, 1),
                "items": plan.items, "waves": plan.waves, "ms": ms, "ms_ci95": st["ci95"],
-               "tflops": round(tf, 3), "frac_peak": round(tf / PEAK_F64, 4),
+               "tflops": round(tf, 3), "frac_peak": round(tf / (PEAK_F32 if f32 else PEAK_F64), 4),
                "predicted_ms": round(plan.predicted_ms, 3),
                "q_cu_words": plan.q_cu_words, "thm1_words": plan.thm1_words,
                "q_cu_over_thm1": round(plan.q_cu_words / plan.thm1_words, 4),
@@ -454,6 +458,16 @@ def run_sweep(torch, cm, synth, dev, stream, reps):
         row = one(m, n, k, plan, f"tile {t}")
         row["tile_words_per_cu"] = plan.tile_m * plan.tile_n * plan.wg_per_cu
         out["tiles"].append(row)
+    # the paper's limited / extra-memory shapes for p = 256 CUs of S_CU words
+    for dtype, dt in (("f64", cm.COSMA_F64), ("f32", cm.COSMA_F32)):
+        rc, probe = cm.cosma_plan_query(1024, 1024, 1024, dt)
+        for name, (m, n, k) in synth.memory_scenarios(probe.S_words, 256):
+            rc, plan = cm.cosma_plan_query(m, n, k, dt)
+            cm.check(rc, "plan")
+            row = one(m, n, k, plan, name, dtype)
+            row["scenario"] = name
+            row["dtype"] = dtype
+            out["memory_scenarios"].append(row)
     return out
 
 

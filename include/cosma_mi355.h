@@ -90,8 +90,13 @@ typedef enum {
   COSMA_ERR_NO_MEMORY = -5    /* host allocation failed (planner / batch metadata) */
 } cosma_status;
 
-/* Hardware figures the planner uses (queried from the device, or defaults
-   for MI355X when no device is present). */
+/* Hardware figures the planner uses: the machine model of section 2.1 (p
+   processors with S words of fast memory each) plus the memory level above.
+   With a device, num_cus, lds_bytes_per_cu, vgpr_bytes_per_cu (32-bit
+   registers per CU x 4), l2_bytes_per_xcd, num_xcds and clock_ghz are read
+   from the runtime; hbm_gbps is the published peak.  Without a device all
+   are MI355X defaults (256 CUs, 8 XCDs, 160 KiB LDS, 512 KiB registers and
+   4 MiB L2 per XCD, 2.4 GHz, 8000 GB/s). */
 typedef struct {
   int32_t num_cus;            /* compute units ("processors") */
   int32_t num_xcds;           /* accelerator dies; each has its own L2 */

@@ -72,10 +72,27 @@ cosma_device_facts device_facts(int* status) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
       if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) d.status = COSMA_ERR_UNSUPPORTED;
+      // the machine model's processor count and fast memory (section 2.1):
+      // CUs, and per CU the LDS and the register file (32-bit registers,
+      // arch + accumulation); per XCD its L2 and the XCD count for Q_EA.
+      // The HBM rate stays the published peak (the clock and bus width the
+      // runtime reports do not give it directly).
       if (prop.multiProcessorCount > 0) d.facts.num_cus = prop.multiProcessorCount;
       if (prop.maxSharedMemoryPerMultiProcessor > 0)
         d.facts.lds_bytes_per_cu = (int64_t)prop.maxSharedMemoryPerMultiProcessor;
+      if (prop.regsPerMultiprocessor > 0) {
+        // gfx950's file holds, per lane, as many accumulation registers as
+        // architectural ones; runtimes differ in whether they count both
+        // (ROCm 7.2: 131072 per CU) or the architectural half (7.0: 65536)
+        int64_t regs = prop.regsPerMultiprocessor;
+        if (regs == 4 * 64 * 256) regs *= 2;
+        d.facts.vgpr_bytes_per_cu = regs * 4;
+      }
+      if (prop.l2CacheSize > 0) d.facts.l2_bytes_per_xcd = (int64_t)prop.l2CacheSize;
       if (prop.clockRate > 0) d.facts.clock_ghz = prop.clockRate * 1e-6;
+      int xcc = 0;
+      if (hipDeviceGetAttribute(&xcc, hipDeviceAttributeNumberOfXccs, dev) == hipSuccess && xcc > 0)
+        d.facts.num_xcds = xcc;
     } else {
       d.status = COSMA_ERR_HIP;
     }

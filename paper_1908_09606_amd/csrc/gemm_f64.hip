@@ -56,24 +56,36 @@ struct F64Tile {
 // and the last partial round).
 enum LoadMode { LOAD_VEC = 0, LOAD_SCALAR = 1, LOAD_CHECKED = 2 };
 
+// Per-thread operand pointers of a work item at k = 0: chunk i of A is
+// row c / (BK / 2), columns 2 (c % (BK / 2)) + {0, 1} of the panel, with
+// c = t + NT i, i.e. pa + i (NT / (BK / 2)) lda; chunk i of B is row
+// c / (BN / 2), i.e. pb + i (NT / (BN / 2)) ldb.  A round then adds one
+// scalar offset per chunk.
+template <class TL, int BM, int BN, int BK>
+__device__ __forceinline__ void operand_bases(const GemmArgs& g, int64_t row0, int64_t col0,
+                                              const double*& pa, const double*& pb) {
+  static_assert(TL::NT % (BK / 2) == 0 && TL::NT % (BN / 2) == 0, "chunk rows");
+  const int t = threadIdx.x;
+  pa = static_cast<const double*>(g.A) + (row0 + t / (BK / 2)) * g.lda + (t % (BK / 2)) * 2;
+  pb = static_cast<const double*>(g.B) + (int64_t)(t / (BN / 2)) * g.ldb + col0 +
+       (t % (BN / 2)) * 2;
+}
+
 template <class TL, int BM, int BN, int BK, int MODE>
 __device__ __forceinline__ void load_a(const GemmArgs& g, int64_t row0, int64_t k0, int64_t kend,
-                                       d2 (&ra)[TL::A_CHUNKS]) {
-  const double* __restrict__ A = static_cast<const double*>(g.A);
+                                       const double* pa, d2 (&ra)[TL::A_CHUNKS]) {
   const int t = threadIdx.x;
 #pragma unroll
   for (int i = 0; i < TL::A_CHUNKS; ++i) {
-    const int c = t + TL::NT * i;
-    const int r = c / (BK / 2);
-    const int kk = (c % (BK / 2)) * 2;
-    const int64_t gr = row0 + r, gk = k0 + kk;
-    const double* p = A + gr * g.lda + gk;
+    const double* p = pa + (int64_t)i * (TL::NT / (BK / 2)) * g.lda + k0;
     if (MODE == LOAD_VEC) {
       ra[i] = *reinterpret_cast<const d2*>(p);
     } else if (MODE == LOAD_SCALAR) {
       ra[i].x = p[0];
       ra[i].y = p[1];
     } else {
+      const int c = t + TL::NT * i;
+      const int64_t gr = row0 + c / (BK / 2), gk = k0 + (c % (BK / 2)) * 2;
       const bool rin = gr < g.m;
       ra[i].x = (rin && gk < kend) ? p[0] : 0.0;
       ra[i].y = (rin && gk + 1 < kend) ? p[1] : 0.0;
@@ -83,22 +95,19 @@ __device__ __forceinline__ void load_a(const GemmArgs& g, int64_t row0, int64_t 
 
 template <class TL, int BM, int BN, int BK, int MODE>
 __device__ __forceinline__ void load_b(const GemmArgs& g, int64_t col0, int64_t k0, int64_t kend,
-                                       d2 (&rb)[TL::B_CHUNKS]) {
-  const double* __restrict__ B = static_cast<const double*>(g.B);
+                                       const double* pb, d2 (&rb)[TL::B_CHUNKS]) {
   const int t = threadIdx.x;
 #pragma unroll
   for (int i = 0; i < TL::B_CHUNKS; ++i) {
-    const int c = t + TL::NT * i;
-    const int r = c / (BN / 2);
-    const int nn = (c % (BN / 2)) * 2;
-    const int64_t gk = k0 + r, gc = col0 + nn;
-    const double* p = B + gk * g.ldb + gc;
+    const double* p = pb + (k0 + (int64_t)i * (TL::NT / (BN / 2))) * g.ldb;
     if (MODE == LOAD_VEC) {
       rb[i] = *reinterpret_cast<const d2*>(p);
     } else if (MODE == LOAD_SCALAR) {
       rb[i].x = p[0];
       rb[i].y = p[1];
     } else {
+      const int c = t + TL::NT * i;
+      const int64_t gk = k0 + c / (BN / 2), gc = col0 + (c % (BN / 2)) * 2;
       const bool kin = gk < kend;
       rb[i].x = (kin && gc < g.n) ? p[0] : 0.0;
       rb[i].y = (kin && gc + 1 < g.n) ? p[1] : 0.0;
@@ -114,33 +123,34 @@ __device__ __forceinline__ void load_b(const GemmArgs& g, int64_t col0, int64_t 
 template <class TL, int BM, int BN, int BK, bool FAST>
 __device__ __forceinline__ void load_round(const GemmArgs& g, int64_t row0, int64_t col0,
                                            int64_t k0, int64_t kend, bool a_in, bool b_in,
+                                           const double* pa, const double* pb,
                                            d2 (&ra)[TL::A_CHUNKS], d2 (&rb)[TL::B_CHUNKS]) {
   const bool k_in = k0 + BK <= kend;
   if (FAST) {
     if (k_in) {
-      load_a<TL, BM, BN, BK, LOAD_VEC>(g, row0, k0, kend, ra);
-      load_b<TL, BM, BN, BK, LOAD_VEC>(g, col0, k0, kend, rb);
+      load_a<TL, BM, BN, BK, LOAD_VEC>(g, row0, k0, kend, pa, ra);
+      load_b<TL, BM, BN, BK, LOAD_VEC>(g, col0, k0, kend, pb, rb);
     } else {
-      load_a<TL, BM, BN, BK, LOAD_CHECKED>(g, row0, k0, kend, ra);
-      load_b<TL, BM, BN, BK, LOAD_CHECKED>(g, col0, k0, kend, rb);
+      load_a<TL, BM, BN, BK, LOAD_CHECKED>(g, row0, k0, kend, pa, ra);
+      load_b<TL, BM, BN, BK, LOAD_CHECKED>(g, col0, k0, kend, pb, rb);
     }
     return;
   }
   if (a_in && k_in) {
     if (g.vec_a)
-      load_a<TL, BM, BN, BK, LOAD_VEC>(g, row0, k0, kend, ra);
+      load_a<TL, BM, BN, BK, LOAD_VEC>(g, row0, k0, kend, pa, ra);
     else
-      load_a<TL, BM, BN, BK, LOAD_SCALAR>(g, row0, k0, kend, ra);
+      load_a<TL, BM, BN, BK, LOAD_SCALAR>(g, row0, k0, kend, pa, ra);
   } else {
-    load_a<TL, BM, BN, BK, LOAD_CHECKED>(g, row0, k0, kend, ra);
+    load_a<TL, BM, BN, BK, LOAD_CHECKED>(g, row0, k0, kend, pa, ra);
   }
   if (b_in && k_in) {
     if (g.vec_b)
-      load_b<TL, BM, BN, BK, LOAD_VEC>(g, col0, k0, kend, rb);
+      load_b<TL, BM, BN, BK, LOAD_VEC>(g, col0, k0, kend, pb, rb);
     else
-      load_b<TL, BM, BN, BK, LOAD_SCALAR>(g, col0, k0, kend, rb);
+      load_b<TL, BM, BN, BK, LOAD_SCALAR>(g, col0, k0, kend, pb, rb);
   } else {
-    load_b<TL, BM, BN, BK, LOAD_CHECKED>(g, col0, k0, kend, rb);
+    load_b<TL, BM, BN, BK, LOAD_CHECKED>(g, col0, k0, kend, pb, rb);
   }
 }
 
@@ -190,19 +200,21 @@ __device__ __forceinline__ void f64_tile_body(const GemmArgs& g, const ItemCoord
 #pragma unroll
     for (int j = 0; j < TL::NI; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
+  const double* pa;
+  const double* pb;
+  operand_bases<TL, BM, BN, BK>(g, row0, col0, pa, pb);
   d2 ra[TL::A_CHUNKS], rb[TL::B_CHUNKS];
   if (nk > 0) {
-    load_round<TL, BM, BN, BK, FAST>(g, row0, col0, kbeg, kend, a_in, b_in, ra, rb);
+    load_round<TL, BM, BN, BK, FAST>(g, row0, col0, kbeg, kend, a_in, b_in, pa, pb, ra, rb);
     store_round<TL, BM, BN, BK>(As[0], Bs[0], ra, rb);
   }
   __syncthreads();
-
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int cur = (int)(kt & 1);
     const bool more = kt + 1 < nk;
     if (more)
-      load_round<TL, BM, BN, BK, FAST>(g, row0, col0, kbeg + (kt + 1) * BK, kend, a_in, b_in, ra,
-                                       rb);
+      load_round<TL, BM, BN, BK, FAST>(g, row0, col0, kbeg + (kt + 1) * BK, kend, a_in, b_in, pa,
+                                       pb, ra, rb);
     const double* __restrict__ as = As[cur];
     const double* __restrict__ bs = Bs[cur];
 #pragma unroll
@@ -227,7 +239,8 @@ __device__ __forceinline__ void f64_tile_body(const GemmArgs& g, const ItemCoord
         for (int i = 0; i < TL::MI; ++i)
 #pragma unroll
           for (int j = 0; j < TL::NI; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+            acc[i][j] =
+                __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
     }
     if (more) store_round<TL, BM, BN, BK>(As[cur ^ 1], Bs[cur ^ 1], ra, rb);
     __syncthreads();

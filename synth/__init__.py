@@ -137,6 +137,43 @@ def batch_dims(count: int, seed: int, lo: int = 64, hi: int = 4096) -> np.ndarra
     return out
 
 
+def memory_scenarios(S_words: float, p: int):
+    """The paper's memory-scaling shapes (section 8, "Selection of
+    Benchmarks"; figure captions of section 9) for p processors with S
+    words each: "limited memory" keeps p S / I fixed, "extra memory"
+    p^(2/3) S / I, with I = mn + mk + nk the input size; here both constants
+    are 1.  Shapes: square (n = sqrt(I / 3)); largeK, the RPA water shape
+    m = n = 136 w, k = 228 w^2 (section 8's application benchmark); largeM,
+    its transpose m = 228 w^2, n = k = 136 w; flat, the rank-256 update with
+    k = 256.  Also the square sizes around the switch of eq. optTileShape,
+    mnk / p = S^(3/2) (0.75x, 1x, 1.3x).  Returns [(name, (m, n, k))]."""
+    import math
+
+    def rpa_w(I):
+        lo, hi = 0.01, 1e4
+        for _ in range(200):
+            w = 0.5 * (lo + hi)
+            if 2 * 136 * 228 * w ** 3 + 136 * 136 * w * w > I:
+                hi = w
+            else:
+                lo = w
+        return w
+
+    out = []
+    for tag, I in (("limited", p * S_words), ("extra", p ** (2.0 / 3.0) * S_words)):
+        w = rpa_w(I)
+        mm, kk = round(136 * w), round(228 * w * w)
+        fl = round(-256 + math.sqrt(256 * 256 + I))
+        out += [(f"square {tag}", (round(math.sqrt(I / 3)),) * 3),
+                (f"largeK {tag}", (mm, mm, kk)), (f"largeM {tag}", (kk, mm, mm)),
+                (f"flat {tag}", (fl, fl, 256))]
+    sw = (p * S_words ** 1.5) ** (1.0 / 3.0)
+    out += [("optTileShape switch x0.75", (round(0.75 * sw),) * 3),
+            ("optTileShape switch", (round(sw),) * 3),
+            ("optTileShape switch x1.3", (round(1.3 * sw),) * 3)]
+    return out
+
+
 # ------------------------------------------------------------------ device fill
 import ctypes as _ct
 import os as _os

@@ -222,3 +222,41 @@ def test_plan_cache_under_concurrent_queries():
         got = list(ex.map(plan, order))
     for i, g in zip(order, got):
         assert g == serial[i], shapes[i]
+
+
+def test_memory_scaling_scenarios_follow_the_regime():
+    """The paper's limited / extra-memory shapes (section 8) for p = 256 CUs
+    of S_CU words: the recipe meets its definition (p S / I = 1 and
+    p^(2/3) S / I = 1, I = mn + mk + nk); eq. optTileShape's a is sqrt(S) on
+    the limited-memory squares and (mnk / p)^(1/3) < sqrt(S) on the
+    extra-memory ones and below the switch; every shape has mn / S < p, so
+    the plans sit in the k-cut regime of section 6.2, and the shapes whose
+    unsplit tiles would fill under a quarter of the machine cut k (the flat
+    rank-256 updates keep k whole: rounds stay at least 256 long)."""
+    import math
+    import synth
+    for dtype, S in (("f64", 86016.0), ("f32", 172032.0)):
+        scen = dict(synth.memory_scenarios(S, 256))
+        for name, (m, n, k) in scen.items():
+            I = m * n + m * k + n * k
+            if "limited" in name:
+                assert abs(I / (256 * S) - 1) < 0.02, (name, I)
+            elif "extra" in name:
+                assert abs(I / (256 ** (2 / 3) * S) - 1) < 0.02, (name, I)
+            rc, p = cm.cosma_plan_query(m, n, k, dtype)
+            assert rc == 0 and p.S_words == S
+            cube = (m * n * k / 256) ** (1 / 3)
+            assert p.a_par == pytest.approx(min(math.sqrt(S), cube), rel=1e-12)
+            assert p.regime == 1 and p.p1 < 256
+            assert p.q_cu_words >= p.thm1_words * (1 - 1e-12)
+            tiles = -(-m // p.tile_m) * -(-n // p.tile_n)
+            if k >= 2048 and 4 * tiles <= 256 * p.wg_per_cu:
+                assert p.p_k > 1, (dtype, name, p.p_k)
+            if name.startswith("flat"):
+                assert p.p_k == 1
+        assert scen["square limited"][0] > 0
+        rc, p = cm.cosma_plan_query(*scen["square limited"], dtype)
+        assert p.a_par == pytest.approx(math.sqrt(S))
+        for nm in ("square extra", "optTileShape switch x0.75"):
+            rc, p = cm.cosma_plan_query(*scen[nm], dtype)
+            assert p.a_par < math.sqrt(S) * 0.9, nm

@@ -61,3 +61,57 @@ def test_every_tile_on_one_shape(gpu, tile):
     log(f"f64 {m}x{n}x{k} tile {plan.tile_m}x{plan.tile_n}")
     err = _run_and_check(m, n, k, plan, seed=7 + tile)
     log(f"  sampled err={err:.3e}")
+
+
+def _scenarios():
+    out = []
+    for dtype, S in (("f64", 86016), ("f32", 172032)):
+        for name, shape in synth.memory_scenarios(S, 256):
+            out.append((dtype, name, shape))
+    return out
+
+
+@pytest.mark.parametrize("case", _scenarios(), ids=lambda c: f"{c[0]}-{c[1].replace(' ', '_')}")
+def test_memory_scaling_scenarios(gpu, case):
+    """The paper's limited- and extra-memory shapes for p = 256 CUs of S_CU
+    words (square, largeK, largeM, flat) and the sizes around the switch of
+    eq. optTileShape, FP64 and FP32, under the planner's own plan: the plan
+    follows the regime (checked on the host in test_planner.py) and every
+    result matches the oracle on 65,536 sampled entries plus the edge tiles."""
+    import torch
+    from gpu_util import fullsize_check
+    dtype, name, (m, n, k) = case
+    rc, plan = cm.cosma_plan_query(m, n, k, dtype)
+    assert rc == 0
+    log(f"{dtype} {name} {m}x{n}x{k}: a {plan.a_par:.0f} (sqrt S {plan.S_words ** 0.5:.0f}) "
+        f"p1 {plan.p1:.1f} tile {plan.tile_m}x{plan.tile_n} p_k {plan.p_k}")
+    f32 = dtype == "f32"
+    dist = synth.UNIFORM_F32 if f32 else synth.UNIFORM_F64
+    seed = 60 + m % 31
+    _, A = device_matrix(m, k, seed, synth.STREAM_A, dist)
+    _, B = device_matrix(k, n, seed, synth.STREAM_B, dist)
+    C = torch.full((m, n), float("nan"), dtype=A.dtype, device="cuda")
+    cm.gemm(A, B, C, dtype=dtype)
+    torch.cuda.synchronize()
+    fullsize_check(C, m, n, k, seed, dist, plan,
+                   oracle.fp32_bound(k) if f32 else oracle.fp64_bound(k))
+    del A, B, C
+    torch.cuda.empty_cache()
+
+
+def test_device_facts_come_from_the_runtime(gpu):
+    """The planner's machine model reads the processor count and each CU's
+    fast memory (LDS + register file), the per-XCD L2 and the XCD count from
+    the runtime; on MI355X they equal the published figures."""
+    import torch
+    rc, f = cm.cosma_device_query()
+    assert rc == 0
+    props = torch.cuda.get_device_properties(0)
+    assert f.num_cus == props.multi_processor_count
+    log(f"device facts: {f.num_cus} CUs, {f.num_xcds} XCDs, LDS {f.lds_bytes_per_cu}, "
+        f"VGPR {f.vgpr_bytes_per_cu}, L2/XCD {f.l2_bytes_per_xcd}, {f.clock_ghz} GHz")
+    assert (f.num_cus, f.num_xcds) == (256, 8)
+    assert f.lds_bytes_per_cu == 160 * 1024 and f.vgpr_bytes_per_cu == 512 * 1024
+    assert f.l2_bytes_per_xcd == 4 * 1024 * 1024
+    rc, p = cm.cosma_plan_query(4096, 4096, 4096, "f64")
+    assert p.S_words == (f.lds_bytes_per_cu + f.vgpr_bytes_per_cu) / 8

@@ -3,9 +3,10 @@
 //
 // Every problem gets a tile and a split factor p_k from a policy; problems
 // that share a tile form one group, whose (problem, split, tile) work items
-// run in one persistent launch with workgroups pulling items from a device
-// counter.  Problems are ordered longest item first, so the tail of a launch
-// is made of short items.  A problem whose items would be long against the
+// run in one persistent launch with workgroups pulling items from device
+// counters, one per XCD chunk of the group's problems (a problem's panels
+// then meet in one L2).  Within a chunk problems are ordered longest item
+// first, so the tail of a launch is made of short items.  A problem whose items would be long against the
 // launch's share of work per resident slot is cut in k: the batch analogue
 // of section 6.2, where k is cut once the processors outnumber the
 // independent (i, j) domains.  Its partials go to workspace planes and one
@@ -76,6 +77,8 @@ struct Group {
   int tile_id;
   int64_t base, items;  // batch-wide item range
   int grid;
+  int chunks;                       // XCD chunks (BatchArgs)
+  int64_t chunk[kBatchChunks + 1];  // chunk boundaries, launch-relative
 };
 
 // A batch under one policy: problems in launch order, groups, reduction list.
@@ -176,21 +179,40 @@ void build_layout(const std::vector<Input>& in, int dtype, int policy, const cos
     std::vector<BatchProblem*> group;
     for (int i : by_tile[t]) group.push_back(&work[i]);
     choose_splits(group, dtype, t, f, policy != POLICY_NO_SPLIT);
+    // One chunk per XCD: whole problems, largest first, each to the chunk
+    // with the least work so far; inside a chunk longest items first (the
+    // rounds per item decide an item's duration).
     std::vector<int>& ps = by_tile[t];
-    // longest items first: the rounds per item decide an item's duration
-    std::stable_sort(ps.begin(), ps.end(),
-                     [&](int a, int c) { return work[a].k_split > work[c].k_split; });
+    auto rounds = [&](int i) {
+      const BatchProblem& p = work[i];
+      return (double)p.tiles_m * p.tiles_n * p.splits * (double)p.k_split;
+    };
+    std::stable_sort(ps.begin(), ps.end(), [&](int a, int c) { return rounds(a) > rounds(c); });
     Group g;
     g.tile_id = t;
     g.base = L.items;
+    g.chunks = std::max(1, std::min(kBatchChunks, f.num_xcds));
+    std::vector<std::vector<int>> bins(g.chunks);
+    std::vector<double> load(g.chunks, 0.0);
     for (int i : ps) {
-      BatchProblem p = work[i];
-      p.first = L.items;
-      L.items += (int64_t)p.tiles_m * p.tiles_n * p.splits;
-      L.input_of.push_back(in[i].index);
-      L.probs.push_back(p);
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      bins[x].push_back(i);
+      load[x] += rounds(i);
+    }
+    for (int x = 0; x < g.chunks; ++x) {
+      std::stable_sort(bins[x].begin(), bins[x].end(),
+                       [&](int a, int c) { return work[a].k_split > work[c].k_split; });
+      g.chunk[x] = L.items - g.base;
+      for (int i : bins[x]) {
+        BatchProblem p = work[i];
+        p.first = L.items;
+        L.items += (int64_t)p.tiles_m * p.tiles_n * p.splits;
+        L.input_of.push_back(in[i].index);
+        L.probs.push_back(p);
+      }
     }
     g.items = L.items - g.base;
+    for (int x = g.chunks; x <= kBatchChunks; ++x) g.chunk[x] = g.items;
     const int64_t slots = (int64_t)f.num_cus * batched_occupancy(dtype, t);
     g.grid = (int)std::max<int64_t>(1, std::min<int64_t>(slots, g.items));
     L.groups.push_back(g);
@@ -215,7 +237,7 @@ DeviceParts parts_of(const Layout& L) {
   DeviceParts d;
   d.probs = up256(std::max<size_t>(1, L.probs.size()) * sizeof(BatchProblem));
   d.map = up256(std::max<int64_t>(1, L.items) * sizeof(int32_t));
-  d.counters = 256;
+  d.counters = up256(std::max<size_t>(1, L.groups.size()) * kBatchChunks * sizeof(unsigned));
   d.partials = L.partial_bytes;
   d.total = d.probs + d.map + d.counters + d.partials;
   return d;
@@ -251,7 +273,7 @@ int enqueue_launches(int dtype, const Layout& L, const Placed& pl, const std::ve
   if (!L.probs.empty()) {
     if (launch_batch_expand(pl.probs, (int64_t)L.probs.size(), pl.map, s) != hipSuccess)
       return COSMA_ERR_HIP;
-    if (launch_reset_counters(pl.counters, (int)L.groups.size(), s) != hipSuccess)
+    if (launch_reset_counters(pl.counters, (int)L.groups.size() * kBatchChunks, s) != hipSuccess)
       return COSMA_ERR_HIP;
   }
   for (size_t gi = 0; gi < L.groups.size(); ++gi) {
@@ -261,7 +283,10 @@ int enqueue_launches(int dtype, const Layout& L, const Placed& pl, const std::ve
     a.map = pl.map;
     a.base = g.base;
     a.count = g.items;
-    a.counter = pl.counters + gi;
+    a.counter = pl.counters + gi * kBatchChunks;
+    a.chunks = g.chunks;
+    a.pad_ = 0;
+    for (int x = 0; x <= kBatchChunks; ++x) a.chunk[x] = g.chunk[x];
     const hipError_t e = dtype == F64 ? launch_batched_f64(g.tile_id, a, g.grid, s)
                                       : launch_batched_f32(g.tile_id, a, g.grid, s);
     if (e != hipSuccess) return COSMA_ERR_HIP;

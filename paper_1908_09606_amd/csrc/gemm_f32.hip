@@ -28,6 +28,7 @@
 //                  acc[v] = D[4g + v][r]
 #include <hip/hip_runtime.h>
 
+#include "batch_device.hpp"
 #include "kernels.hpp"
 #include "tiles.hpp"
 
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE
 }
 
 // Persistent batched form: every workgroup takes (problem, split, tile)
-// items from the device counter until the list is exhausted; each item is
+// items from the device counters until every chunk is drained; each item is
 // computed exactly as by gemm_f32_kernel under the problem's split.
 template <int BM, int BN, int BK, int WM, int WN, int WPE, int BLK>
 __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void gemm_f32_batched_kernel(
@@ -318,31 +319,17 @@ __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE
   using TL = F32Tile<BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) float As[2][TL::A_STAGE];
   __shared__ __attribute__((aligned(16))) float Bs[2][TL::B_STAGE];
-  __shared__ unsigned next;
+  __shared__ int64_t next;
+  int step = 0;
   for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(b.counter, 1u);
+    if (threadIdx.x == 0) next = batch_take(b, step);
     __syncthreads();
-    const unsigned it = next;
+    const int64_t it = uniform_i64(next);
     __syncthreads();
-    if ((int64_t)it >= b.count) return;
-    const int64_t gi = b.base + (int64_t)it;
-    const BatchProblem& p = b.probs[b.map[gi]];
+    if (it < 0) return;
     GemmArgs g;
-    g.A = p.A; g.B = p.B; g.C = p.C; g.P = p.P;
-    g.lda = p.lda; g.ldb = p.ldb; g.ldc = p.ldc;
-    g.m = p.m; g.n = p.n; g.k = p.k;
-    g.k_split = p.k_split; g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.splits = p.splits;
-    g.ldp = p.n; g.split_stride = p.m * p.n;
-    g.alpha = p.alpha; g.beta = p.beta;
-    g.group_m = 1; g.num_xcds = 1;
-    g.vec_a = p.vec_a; g.vec_b = p.vec_b;
-    const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
-    const int64_t local = gi - p.first;
     ItemCoord ic;
-    ic.split = local / tiles;
-    const int64_t t = local - ic.split * tiles;
-    ic.tile_row = t / p.tiles_n;
-    ic.tile_col = t - ic.tile_row * p.tiles_n;
+    batch_item(b, (unsigned)it, g, ic);
     f32_tile<BM, BN, BK, WM, WN, BLK>(g, ic, As, Bs);
   }
 }

@@ -21,6 +21,7 @@
 // 32-byte run.
 #include <hip/hip_runtime.h>
 
+#include "batch_device.hpp"
 #include "kernels.hpp"
 #include "tiles.hpp"
 
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE
 }
 
 // Persistent batched form: workgroups take (problem, split, tile) items from
-// the device counter until the list is exhausted; every item is computed as
+// the device counters until every chunk is drained; every item is computed as
 // by gemm_f64_kernel under the problem's split (partials to its planes).
 template <int BM, int BN, int BK, int WM, int WN, int WPE>
 __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void gemm_f64_batched_kernel(
@@ -316,31 +317,17 @@ __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE
   using TL = F64Tile<BM, BN, BK, WM, WN>;
   __shared__ __attribute__((aligned(16))) double As[2][TL::A_STAGE];
   __shared__ __attribute__((aligned(16))) double Bs[2][TL::B_STAGE];
-  __shared__ unsigned next;
+  __shared__ int64_t next;
+  int step = 0;
   for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(b.counter, 1u);
+    if (threadIdx.x == 0) next = batch_take(b, step);
     __syncthreads();
-    const unsigned it = next;
+    const int64_t it = uniform_i64(next);
     __syncthreads();
-    if ((int64_t)it >= b.count) return;
-    const int64_t gi = b.base + (int64_t)it;
-    const BatchProblem& p = b.probs[b.map[gi]];
+    if (it < 0) return;
     GemmArgs g;
-    g.A = p.A; g.B = p.B; g.C = p.C; g.P = p.P;
-    g.lda = p.lda; g.ldb = p.ldb; g.ldc = p.ldc;
-    g.m = p.m; g.n = p.n; g.k = p.k;
-    g.k_split = p.k_split; g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.splits = p.splits;
-    g.ldp = p.n; g.split_stride = p.m * p.n;
-    g.alpha = p.alpha; g.beta = p.beta;
-    g.group_m = 1; g.num_xcds = 1;
-    g.vec_a = p.vec_a; g.vec_b = p.vec_b;
-    const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
-    const int64_t local = gi - p.first;
     ItemCoord ic;
-    ic.split = local / tiles;
-    const int64_t t = local - ic.split * tiles;
-    ic.tile_row = t / p.tiles_n;
-    ic.tile_col = t - ic.tile_row * p.tiles_n;
+    batch_item(b, (unsigned)it, g, ic);
     f64_tile<BM, BN, BK, WM, WN>(g, ic, As, Bs);
   }
 }

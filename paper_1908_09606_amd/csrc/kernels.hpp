@@ -47,12 +47,20 @@ struct BatchProblem {
   int32_t pad_;
 };
 
+// A launch's items are cut into contiguous chunks, one per XCD, each a run
+// of whole problems: the workgroups of XCD x (blocks b with b % chunks == x)
+// take items of chunk x first, so a problem's panels are fetched into one
+// L2, and then help drain the other chunks in turn.
+constexpr int kBatchChunks = 8;
 struct BatchArgs {
   const BatchProblem* probs;  // every problem of the batch
   const int32_t* map;         // problem index of every item of the batch
   int64_t base;               // batch-wide number of this launch's first item
   int64_t count;              // items in this launch
-  unsigned* counter;          // next item to hand out (reset before the launch)
+  unsigned* counter;          // per chunk: next item to hand out (reset before the launch)
+  int32_t chunks;             // chunks in use, 1..kBatchChunks
+  int32_t pad_;
+  int64_t chunk[kBatchChunks + 1];  // chunk x = launch items [chunk[x], chunk[x + 1])
 };
 
 // Problems travel to device memory inside kernel arguments (no host copy,

@@ -289,9 +289,14 @@ COSMA_API int cosma_workspace_size_batched(int64_t count, const int64_t* m, cons
    uploads the descriptors and captures the launches into a HIP graph.  The
    handle owns its device memory (allocated here, never on the replay path)
    and graph until cosma_batch_destroy.  Pointers and sizes are fixed at
-   creation; replays read the current contents of A, B and C.  When every
-   beta is zero (and COSMA_AUTOTUNE is not 0) the autotuner runs the batch
-   once per candidate policy on `stream` and keeps the fastest. */
+   creation; replays read the current contents of A, B and C.  Inside the
+   graph the tile variants' launches run concurrently.  When every beta is
+   zero (and COSMA_AUTOTUNE is not 0) the autotuner times the batch on
+   `stream`: first once per policy (below), then, from the fastest, class
+   by class of problems (m n and k each binned by factors of four, the
+   eight classes with the most flops first) it tries the other tiles and
+   twice / half the current split factors, keeping a change that is more
+   than 1 % faster.  Otherwise the planner's batch model decides. */
 COSMA_API int cosma_batch_create(int64_t count, const int64_t* m, const int64_t* n, const int64_t* k,
                        const double* alpha, const void* const* A, const int64_t* lda,
                        const void* const* B, const int64_t* ldb, const double* beta,
@@ -304,7 +309,7 @@ COSMA_API int cosma_batch_run(void* handle, void* stream);
    memory and graph.  Replays captured into a caller's graph must be
    finished by the caller. */
 COSMA_API int cosma_batch_destroy(void* handle);
-/* Policy the autotuner kept (0 = the planner's batch model per problem,
+/* Policy the autotuner started its refinement from (0 = the planner's batch model per problem,
    1 = all 64x64, 2 = all 128x128, 3 = size threshold, each with the model's
    splits; 4 = the model's tiles with k never cut), number of persistent
    launches (one per tile variant), work items, and the timed milliseconds
@@ -312,6 +317,10 @@ COSMA_API int cosma_batch_destroy(void* handle);
    COSMA_AUTOTUNE=0). */
 COSMA_API int cosma_batch_info(void* handle, int* policy, int* groups, int64_t* items,
                                double* policy_ms, int policy_ms_len);
+/* The autotuner's refinement: trials timed after the policies, the fastest
+   policy's milliseconds and the kept assignment's (all 0 without tuning).
+   Any output pointer may be NULL. */
+COSMA_API int cosma_batch_tuning(void* handle, int* trials, double* seed_ms, double* tuned_ms);
 /* Tile id (menu index of the batch's dtype) each input problem runs with, or
    -1 for problems without products (m, n or k zero, or alpha zero); count
    must equal the count given at creation. */

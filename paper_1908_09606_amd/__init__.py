@@ -41,7 +41,7 @@ COSMA_ERR_NO_MEMORY = -5
 EXPORTED = [
     "cosma_gemm", "cosma_gemm_planned", "cosma_gemm_noalloc", "cosma_gemm_ex", "cosma_workspace_size_ex", "cosma_pgemm",
     "cosma_gemm_batched", "cosma_batch_create",
-    "cosma_batch_run", "cosma_batch_destroy", "cosma_batch_info", "cosma_batch_tiles",
+    "cosma_batch_run", "cosma_batch_destroy", "cosma_batch_info", "cosma_batch_tuning", "cosma_batch_tiles",
     "cosma_batch_splits", "cosma_workspace_size_batched", "cosma_plan_query", "cosma_plan_query_facts",
     "cosma_plan_make", "cosma_plan_set_slices", "cosma_set_ozaki_spread", "cosma_get_ozaki_spread", "cosma_ozaki2_params", "cosma_tile_count", "cosma_tile_shape", "cosma_device_query",
     "cosma_thm1_bound", "cosma_seq_schedule", "cosma_par_schedule", "cosma_fit_ranks",
@@ -123,6 +123,7 @@ def lib():
                 "cosma_batch_destroy": (i32, [vp]),
                 "cosma_batch_info": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), pi64,
                                            pdbl, i32]),
+                "cosma_batch_tuning": (i32, [vp, ctypes.POINTER(i32), pdbl, pdbl]),
                 "cosma_batch_tiles": (i32, [vp, i64, ctypes.POINTER(ctypes.c_int32)]),
                 "cosma_batch_splits": (i32, [vp, i64, ctypes.POINTER(ctypes.c_int32)]),
                 "cosma_workspace_size_batched": (i32, [i64, pi64, pi64, pi64, pdbl, i32,
@@ -291,6 +292,14 @@ def cosma_batch_info(handle):
     rc = lib().cosma_batch_info(handle, ctypes.byref(pol), ctypes.byref(groups),
                                 ctypes.byref(items), ms, BATCH_POLICIES)
     return rc, pol.value, groups.value, items.value, list(ms)
+
+
+def cosma_batch_tuning(handle):
+    """Returns (status, refinement trials, fastest policy's ms, kept ms)."""
+    trials, seed, tuned = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    rc = lib().cosma_batch_tuning(handle, ctypes.byref(trials), ctypes.byref(seed),
+                                  ctypes.byref(tuned))
+    return rc, trials.value, seed.value, tuned.value
 
 
 def cosma_batch_tiles(handle, count):

@@ -85,6 +85,7 @@ struct Group {
 struct Layout {
   std::vector<BatchProblem> probs;
   std::vector<int> input_of;   // probs[i] came from input problem input_of[i]
+  std::vector<int> in_pos;     // ... at position in_pos[i] of the collected inputs
   std::vector<Group> groups;
   std::vector<int32_t> reduce;  // probs indices with splits > 1
   int64_t items = 0;
@@ -132,9 +133,10 @@ int policy_tile(int policy, int dtype, const BatchProblem& p, const cosma_device
 // items started longest first, a launch is balanced while no item exceeds
 // a quarter of the group's work per slot.  Longer items are cut in k (at
 // least 256 per split, at most 64 splits), as make_plan cuts k into
-// multiples of the tile's round.
-void choose_splits(std::vector<BatchProblem*>& group, int dtype, int tile_id,
-                   const cosma_device_facts& f, bool allow) {
+// multiples of the tile's round.  req[i] > 0 asks for that many splits of
+// group[i] instead (within the same limits).
+void choose_splits(std::vector<BatchProblem*>& group, const std::vector<int>& req_in, int dtype,
+                   int tile_id, const cosma_device_facts& f) {
   int cnt = 0;
   const TileDesc* menu = tile_menu(dtype, &cnt);
   const TileDesc& T = menu[tile_id];
@@ -145,30 +147,48 @@ void choose_splits(std::vector<BatchProblem*>& group, int dtype, int tile_id,
   for (BatchProblem* p : group)
     work += (double)p->tiles_m * p->tiles_n * 2.0 * T.tm * T.tn * (double)p->k / slot_rate;
   const double cap = work / slots / 4.0;
-  for (BatchProblem* p : group) {
+  for (size_t i = 0; i < group.size(); ++i) {
+    BatchProblem* p = group[i];
     const int64_t panels = ceil_div(p->k, T.tk);
-    int64_t req = 1;
-    if (allow && cap > 0.0) {
+    int64_t req = req_in[i];
+    if (req <= 0) {
+      req = 1;
       const double d = 2.0 * T.tm * T.tn * (double)p->k / slot_rate;
-      if (d > cap) req = (int64_t)std::ceil(d / cap);
-      req = std::min<int64_t>(req, std::min<int64_t>(64, p->k / 256));
-      req = std::max<int64_t>(req, 1);
+      if (cap > 0.0 && d > cap) req = (int64_t)std::ceil(d / cap);
     }
+    req = std::min<int64_t>(req, std::min<int64_t>(64, p->k / 256));
+    req = std::max<int64_t>(req, 1);
     p->k_split = ceil_div(panels, req) * T.tk;
     p->splits = (int32_t)ceil_div(p->k, p->k_split);
   }
 }
 
-// Apply a policy: tiles, splits, launch order, item numbering, partials.
-void build_layout(const std::vector<Input>& in, int dtype, int policy, const cosma_device_facts& f,
-                  Layout& L) {
+// Tile and split request of every input problem (split 0: the group's
+// model, choose_splits).  A policy gives the first assignment; the
+// autotuner changes it class by class.
+struct Assignment {
+  std::vector<int> tile, split;
+};
+
+Assignment seed_assignment(const std::vector<Input>& in, int dtype, int policy,
+                           const cosma_device_facts& f) {
+  Assignment a;
+  a.tile.resize(in.size());
+  a.split.assign(in.size(), policy == POLICY_NO_SPLIT ? 1 : 0);
+  for (size_t i = 0; i < in.size(); ++i) a.tile[i] = policy_tile(policy, dtype, in[i].p, f);
+  return a;
+}
+
+// Apply an assignment: tiles, splits, launch order, item numbering, partials.
+void build_layout(const std::vector<Input>& in, int dtype, const Assignment& as,
+                  const cosma_device_facts& f, Layout& L) {
   int cnt = 0;
   const TileDesc* menu = tile_menu(dtype, &cnt);
   std::vector<std::vector<int>> by_tile(cnt);
   std::vector<BatchProblem> work(in.size());
   for (size_t i = 0; i < in.size(); ++i) {
     work[i] = in[i].p;
-    const int t = policy_tile(policy, dtype, work[i], f);
+    const int t = as.tile[i];
     work[i].tiles_m = (int32_t)ceil_div(work[i].m, menu[t].tm);
     work[i].tiles_n = (int32_t)ceil_div(work[i].n, menu[t].tn);
     by_tile[t].push_back((int)i);
@@ -177,8 +197,12 @@ void build_layout(const std::vector<Input>& in, int dtype, int policy, const cos
   for (int t = 0; t < cnt; ++t) {
     if (by_tile[t].empty()) continue;
     std::vector<BatchProblem*> group;
-    for (int i : by_tile[t]) group.push_back(&work[i]);
-    choose_splits(group, dtype, t, f, policy != POLICY_NO_SPLIT);
+    std::vector<int> req;
+    for (int i : by_tile[t]) {
+      group.push_back(&work[i]);
+      req.push_back(as.split[i]);
+    }
+    choose_splits(group, req, dtype, t, f);
     // One chunk per XCD: whole problems, largest first, each to the chunk
     // with the least work so far; inside a chunk longest items first (the
     // rounds per item decide an item's duration).
@@ -208,6 +232,7 @@ void build_layout(const std::vector<Input>& in, int dtype, int policy, const cos
         p.first = L.items;
         L.items += (int64_t)p.tiles_m * p.tiles_n * p.splits;
         L.input_of.push_back(in[i].index);
+        L.in_pos.push_back(i);
         L.probs.push_back(p);
       }
     }
@@ -268,16 +293,33 @@ Placed place(Layout& L, void* base) {
 // Everything after the descriptors are in device memory: the item map,
 // counters, one persistent launch per group, the reduction, beta scaling of
 // problems without products.  Kernel launches only (graph-capture safe).
+// With `side` (a fork event, and a stream and a join event per group after
+// the first; used while capturing) the groups' launches fork from `s` and join it again
+// before the reduction, so a group's workgroups take the CUs that the
+// previous group's last items leave idle.
+struct SideStreams {
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> fork, join;
+};
+
 int enqueue_launches(int dtype, const Layout& L, const Placed& pl, const std::vector<Scale>& scales,
-                     hipStream_t s) {
+                     hipStream_t s, const SideStreams* side = nullptr) {
   if (!L.probs.empty()) {
     if (launch_batch_expand(pl.probs, (int64_t)L.probs.size(), pl.map, s) != hipSuccess)
       return COSMA_ERR_HIP;
     if (launch_reset_counters(pl.counters, (int)L.groups.size() * kBatchChunks, s) != hipSuccess)
       return COSMA_ERR_HIP;
   }
+  // one fork point after the map and counters, before any group's launch
+  const bool fork = side && L.groups.size() > 1 && side->streams.size() + 1 >= L.groups.size();
+  if (fork && hipEventRecord(side->fork[0], s) != hipSuccess) return COSMA_ERR_HIP;
   for (size_t gi = 0; gi < L.groups.size(); ++gi) {
     const Group& g = L.groups[gi];
+    hipStream_t gs = s;
+    if (fork && gi > 0) {
+      gs = side->streams[gi - 1];
+      if (hipStreamWaitEvent(gs, side->fork[0], 0) != hipSuccess) return COSMA_ERR_HIP;
+    }
     BatchArgs a;
     a.probs = pl.probs;
     a.map = pl.map;
@@ -287,10 +329,15 @@ int enqueue_launches(int dtype, const Layout& L, const Placed& pl, const std::ve
     a.chunks = g.chunks;
     a.pad_ = 0;
     for (int x = 0; x <= kBatchChunks; ++x) a.chunk[x] = g.chunk[x];
-    const hipError_t e = dtype == F64 ? launch_batched_f64(g.tile_id, a, g.grid, s)
-                                      : launch_batched_f32(g.tile_id, a, g.grid, s);
+    const hipError_t e = dtype == F64 ? launch_batched_f64(g.tile_id, a, g.grid, gs)
+                                      : launch_batched_f32(g.tile_id, a, g.grid, gs);
     if (e != hipSuccess) return COSMA_ERR_HIP;
   }
+  if (fork)
+    for (size_t gi = 1; gi < L.groups.size(); ++gi)
+      if (hipEventRecord(side->join[gi - 1], side->streams[gi - 1]) != hipSuccess ||
+          hipStreamWaitEvent(s, side->join[gi - 1], 0) != hipSuccess)
+        return COSMA_ERR_HIP;
   for (size_t r0 = 0; r0 < L.reduce.size(); r0 += kReduceList) {
     BatchReduceArgs r;
     r.probs = pl.probs;
@@ -384,6 +431,9 @@ struct Batch {
   int dtype = F32;
   int policy = POLICY_MODEL;
   double policy_ms[kPolicies] = {0};
+  int trials = 0;         // refinement trials the autotuner timed
+  double seed_ms = 0.0;   // best policy's time
+  double tuned_ms = 0.0;  // the kept assignment's time
   std::vector<Input> inputs;
   std::vector<Scale> scales;
   int64_t count = 0;
@@ -404,11 +454,18 @@ void free_device(Batch& b) {
   b.mem = nullptr;
 }
 
-// Lay out a policy, upload it and capture its launches (private stream).
-int materialise(Batch& b, int policy, const cosma_device_facts& f) {
+void destroy_side(SideStreams& side) {
+  for (hipStream_t x : side.streams) hipStreamDestroy(x);
+  for (hipEvent_t e : side.fork) hipEventDestroy(e);
+  for (hipEvent_t e : side.join) hipEventDestroy(e);
+  side = SideStreams();
+}
+
+// Lay out an assignment, upload it and capture its launches (private
+// streams; the tile groups run concurrently inside the graph).
+int materialise(Batch& b, const Assignment& as, const cosma_device_facts& f) {
   free_device(b);
-  build_layout(b.inputs, b.dtype, policy, f, b.layout);
-  b.policy = policy;
+  build_layout(b.inputs, b.dtype, as, f, b.layout);
   const DeviceParts d = parts_of(b.layout);
   if (hipMalloc(&b.mem, d.total) != hipSuccess) {
     b.mem = nullptr;
@@ -422,10 +479,32 @@ int materialise(Batch& b, int policy, const cosma_device_facts& f) {
   hipStream_t cap;
   if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return COSMA_ERR_HIP;
   int rc = COSMA_OK;
-  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+  SideStreams side;
+  for (size_t gi = 1; gi < b.layout.groups.size() && rc == COSMA_OK; ++gi) {
+    hipStream_t x;
+    hipEvent_t e;
+    if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) {
+      rc = COSMA_ERR_HIP;
+      break;
+    }
+    side.streams.push_back(x);
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      rc = COSMA_ERR_HIP;
+      break;
+    }
+    side.join.push_back(e);
+    if (side.fork.empty()) {
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        rc = COSMA_ERR_HIP;
+        break;
+      }
+      side.fork.push_back(e);
+    }
+  }
+  if (rc == COSMA_OK && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
     rc = COSMA_ERR_HIP;
-  } else {
-    rc = enqueue_launches(b.dtype, b.layout, pl, b.scales, cap);
+  if (rc == COSMA_OK) {
+    rc = enqueue_launches(b.dtype, b.layout, pl, b.scales, cap, &side);
     hipGraph_t g = nullptr;
     const hipError_t ee = hipStreamEndCapture(cap, &g);
     if (rc == COSMA_OK && ee == hipSuccess) {
@@ -436,6 +515,7 @@ int materialise(Batch& b, int policy, const cosma_device_facts& f) {
       rc = COSMA_ERR_HIP;
     }
   }
+  destroy_side(side);
   hipStreamDestroy(cap);
   return rc;
 }
@@ -465,6 +545,114 @@ double time_graph(Batch& b, hipStream_t s) {
   hipEventDestroy(e1);
   std::sort(ts, ts + 3);
   return ts[1];
+}
+
+// The splits a layout gave each input, as explicit requests.
+Assignment explicit_assignment(const Layout& L, size_t n_inputs) {
+  Assignment a;
+  a.tile.assign(n_inputs, 0);
+  a.split.assign(n_inputs, 1);
+  for (const Group& g : L.groups)
+    for (size_t i = 0; i < L.probs.size(); ++i)
+      if (L.probs[i].first >= g.base && L.probs[i].first < g.base + g.items) {
+        a.tile[L.in_pos[i]] = g.tile_id;
+        a.split[L.in_pos[i]] = L.probs[i].splits;
+      }
+  return a;
+}
+
+// Autotuner.  Seeds: the policies, each timed on the real batch.  Then,
+// starting from the fastest, problems are taken class by class (classes of
+// m n and of k, a factor of four wide each, heaviest class first), and each
+// class tries the other tiles with a batched form and twice / half its
+// current split factors; a change is kept when the batch gets faster by
+// more than 1 % (the replay timing's noise).
+constexpr int kRefineClasses = 8;
+constexpr double kKeepGain = 0.99;
+
+int autotune(Batch& b, const cosma_device_facts& f, hipStream_t s, Assignment& best) {
+  int rc = COSMA_OK;
+  double best_ms = 1e300;
+  for (int pol = 0; pol < kPolicies; ++pol) {
+    const Assignment a = seed_assignment(b.inputs, b.dtype, pol, f);
+    if ((rc = materialise(b, a, f)) != COSMA_OK) return rc;
+    const double ms = time_graph(b, s);
+    b.policy_ms[pol] = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = explicit_assignment(b.layout, b.inputs.size());
+      b.policy = pol;
+    }
+  }
+  b.seed_ms = best_ms;
+  // classes by log4(m n) and log4(k), heaviest (sum of 2 m n k) first
+  const size_t n_in = b.inputs.size();
+  std::vector<int> cls(n_in);
+  std::vector<std::pair<double, int>> weight;
+  for (size_t i = 0; i < n_in; ++i) {
+    const BatchProblem& p = b.inputs[i].p;
+    const int cm = (int)std::floor(std::log2((double)p.m * (double)p.n) / 2.0);
+    const int ck = (int)std::floor(std::log2((double)p.k) / 2.0);
+    cls[i] = cm * 64 + ck;
+  }
+  for (size_t i = 0; i < n_in; ++i) {
+    auto it = std::find_if(weight.begin(), weight.end(),
+                           [&](const std::pair<double, int>& w) { return w.second == cls[i]; });
+    const BatchProblem& p = b.inputs[i].p;
+    const double fl = 2.0 * (double)p.m * (double)p.n * (double)p.k;
+    if (it == weight.end())
+      weight.emplace_back(fl, cls[i]);
+    else
+      it->first += fl;
+  }
+  std::sort(weight.begin(), weight.end(),
+            [](const std::pair<double, int>& x, const std::pair<double, int>& y) {
+              return x.first > y.first;
+            });
+  int cnt = 0;
+  tile_menu(b.dtype, &cnt);
+  for (size_t c = 0; c < weight.size() && (int)c < kRefineClasses; ++c) {
+    const int key = weight[c].second;
+    std::vector<Assignment> tries;
+    for (int t = 0; t < cnt; ++t) {
+      if (!batched_form(b.dtype, t)) continue;
+      Assignment a = best;
+      bool changed = false;
+      for (size_t i = 0; i < n_in; ++i)
+        if (cls[i] == key && a.tile[i] != t) {
+          a.tile[i] = t;
+          a.split[i] = 0;  // the model's split for the new tile
+          changed = true;
+        }
+      if (changed) tries.push_back(a);
+    }
+    for (int dir = 0; dir < 2; ++dir) {
+      Assignment a = best;
+      bool changed = false;
+      for (size_t i = 0; i < n_in; ++i) {
+        if (cls[i] != key) continue;
+        const int64_t k = b.inputs[i].p.k;
+        const int lim = (int)std::max<int64_t>(1, std::min<int64_t>(64, k / 256));
+        const int v = dir == 0 ? std::min(lim, a.split[i] * 2) : std::max(1, a.split[i] / 2);
+        if (v != a.split[i]) {
+          a.split[i] = v;
+          changed = true;
+        }
+      }
+      if (changed) tries.push_back(a);
+    }
+    for (const Assignment& a : tries) {
+      if ((rc = materialise(b, a, f)) != COSMA_OK) return rc;
+      const double ms = time_graph(b, s);
+      ++b.trials;
+      if (ms < best_ms * kKeepGain) {
+        best_ms = ms;
+        best = explicit_assignment(b.layout, n_in);
+      }
+    }
+  }
+  b.tuned_ms = best_ms;
+  return COSMA_OK;
 }
 
 }  // namespace
@@ -497,20 +685,9 @@ int cosma_batch_create(int64_t count, const int64_t* m, const int64_t* n, const 
       bool all_beta_zero = true;
       for (const Input& q : b->inputs) all_beta_zero = all_beta_zero && q.p.beta == 0.0;
       for (const Scale& s : b->scales) all_beta_zero = all_beta_zero && s.beta == 0.0;
-      int best = POLICY_MODEL;
-      if (autotune_enabled() && all_beta_zero && !b->inputs.empty()) {
-        double best_ms = 1e300;
-        for (int pol = 0; pol < kPolicies && rc == COSMA_OK; ++pol) {
-          rc = materialise(*b, pol, f);
-          if (rc != COSMA_OK) break;
-          const double ms = time_graph(*b, (hipStream_t)stream);
-          b->policy_ms[pol] = ms;
-          if (ms < best_ms) {
-            best_ms = ms;
-            best = pol;
-          }
-        }
-      }
+      Assignment best = seed_assignment(b->inputs, dtype, POLICY_MODEL, f);
+      if (autotune_enabled() && all_beta_zero && !b->inputs.empty())
+        rc = autotune(*b, f, (hipStream_t)stream, best);
       if (rc == COSMA_OK) rc = materialise(*b, best, f);
     }
   }
@@ -563,6 +740,15 @@ int cosma_batch_info(void* handle, int* policy, int* groups, int64_t* items, dou
   return COSMA_OK;
 }
 
+int cosma_batch_tuning(void* handle, int* trials, double* seed_ms, double* tuned_ms) {
+  if (!handle) return COSMA_ERR_INVALID_ARG;
+  Batch* b = static_cast<Batch*>(handle);
+  if (trials) *trials = b->trials;
+  if (seed_ms) *seed_ms = b->seed_ms;
+  if (tuned_ms) *tuned_ms = b->tuned_ms;
+  return COSMA_OK;
+}
+
 int cosma_batch_tiles(void* handle, int64_t count, int32_t* tile_ids) {
   if (!handle || !tile_ids) return COSMA_ERR_INVALID_ARG;
   Batch* b = static_cast<Batch*>(handle);
@@ -596,7 +782,7 @@ int cosma_workspace_size_batched(int64_t count, const int64_t* m, const int64_t*
   int st = COSMA_OK;
   const cosma_device_facts f = device_facts(&st);
   Layout L;
-  build_layout(in, dtype, POLICY_MODEL, f, L);
+  build_layout(in, dtype, seed_assignment(in, dtype, POLICY_MODEL, f), f, L);
   *bytes = in.empty() ? 0 : parts_of(L).total;
   return COSMA_OK;
 }
@@ -617,7 +803,7 @@ int cosma_gemm_batched(int64_t count, const int64_t* m, const int64_t* n, const 
   if (st != COSMA_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   Layout L;
-  build_layout(in, dtype, POLICY_MODEL, f, L);
+  build_layout(in, dtype, seed_assignment(in, dtype, POLICY_MODEL, f), f, L);
   Placed pl{nullptr, nullptr, nullptr, nullptr};
   if (!L.probs.empty()) {
     void* ws = nullptr;

@@ -218,6 +218,11 @@ __device__ __forceinline__ void f64_tile_body(const GemmArgs& g, const ItemCoord
                                        pb, ra, rb);
     const double* __restrict__ as = As[cur];
     const double* __restrict__ bs = Bs[cur];
+    // waves in their product phase issue first: a wave that has reached the
+    // LDS store and barrier of the round waits for the others anyway (about
+    // 1 % on the large FP64 products; the FP32 and BF16x3 loops got slower
+    // with it)
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int h = 0; h < BK / 16; ++h) {
       d4 af[TL::MI];
@@ -243,6 +248,7 @@ __device__ __forceinline__ void f64_tile_body(const GemmArgs& g, const ItemCoord
             acc[i][j] =
                 __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
     }
+    __builtin_amdgcn_s_setprio(0);
     if (more) store_round<TL, BM, BN, BK>(As[cur ^ 1], Bs[cur ^ 1], ra, rb);
     __syncthreads();
   }
@@ -293,6 +299,185 @@ __device__ __forceinline__ void f64_tile(const GemmArgs& g, const ItemCoord& ic,
     f64_tile_body<BM, BN, BK, WM, WN, true>(g, ic, As, Bs);
   else
     f64_tile_body<BM, BN, BK, WM, WN, false>(g, ic, As, Bs);
+}
+
+// ------------------------------------------------- DMA-staged form
+// For launches of full tiles whose rows start 16-byte aligned and whose
+// k ranges are whole rounds (BK = 16): the operands go from global memory
+// straight into LDS (16-byte global-to-LDS loads, no staging registers, no
+// LDS store instructions) into NS stages, NS - 1 rounds ahead of the
+// products, so the latency of the slowest load of a round hides behind
+// NS - 1 rounds of products instead of one.
+//
+// LDS per stage: A as BM rows of 16 doubles (128 bytes, no padding); the
+// eight 16-byte chunks of row r sit at chunk positions c ^ ((r >> 1) & 7),
+// so the 16 rows one MFMA operand read touches cover all banks.  B as 16
+// rows of BN doubles with a row pitch of BN + 4 doubles.  One wave
+// instruction moves 1 KiB: 8 rows of A, or one row of B (BN = 128).
+template <int BM, int BN, int WM, int WN, int NS>
+struct F64Dma {
+  static constexpr int BK = 16;
+  static constexpr int NW = WM * WN;
+  static constexpr int WTM = BM / WM, WTN = BN / WN;
+  static constexpr int MI = WTM / 16, NI = WTN / 16;
+  static constexpr int LDB = BN + 4;               // doubles
+  static constexpr int A_STAGE = BM * BK;          // doubles
+  static constexpr int B_STAGE = BK * LDB;
+  static constexpr int STAGE = A_STAGE + B_STAGE;
+  static constexpr int A_PW = BM / 8 / NW;         // A instructions per wave and round
+  static constexpr int B_PW = BK / NW;             // B instructions per wave and round
+  static constexpr int PW = A_PW + B_PW;
+  static_assert(BN == 128, "one B row per wave instruction");
+  static_assert(A_PW * NW * 8 == BM && B_PW * NW == BK, "instruction split");
+  static_assert(NS >= 2 && (NS - 2) * PW <= 15, "vmcnt immediate");
+  static_assert(NS * STAGE * 8 <= 160 * 1024, "LDS budget");
+};
+
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// s_waitcnt immediate: vmcnt = v, expcnt and lgkmcnt at their maxima.
+constexpr int vm_wait(int v) { return (v & 15) | ((v >> 4) << 14) | (7 << 4) | (15 << 8); }
+
+template <int BM, int BN, int WM, int WN, int NS, int WPE>
+__global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void gemm_f64_dma_kernel(
+    GemmArgs g) {
+  using TL = F64Dma<BM, BN, WM, WN, NS>;
+  constexpr int BK = TL::BK;
+  __shared__ __attribute__((aligned(1024))) double lds[NS * TL::STAGE];
+  const int64_t l = xcd_remap((int64_t)blockIdx.x, (int64_t)gridDim.x, g.num_xcds);
+  const ItemCoord ic = item_coord(l, g.tiles_m, g.tiles_n, g.group_m);
+  const int64_t row0 = ic.tile_row * BM, col0 = ic.tile_col * BN;
+  const int64_t kbeg = ic.split * g.k_split;
+  const int64_t kend = min64(g.k, kbeg + g.k_split);
+  const int64_t nk = (kend - kbeg) / BK;  // whole rounds (checked by the launcher)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int lr = lane & 15, lg = lane >> 4;
+  const double* A = static_cast<const double*>(g.A);
+  const double* B = static_cast<const double*>(g.B);
+
+  // this lane's source of each of the wave's DMA instructions at round 0
+  const double* pa[TL::A_PW];
+#pragma unroll
+  for (int h = 0; h < TL::A_PW; ++h) {
+    const int grp = wave + TL::NW * h;  // rows 8 grp .. 8 grp + 7
+    const int r = 8 * grp + (lane >> 3);
+    const int c = (lane & 7) ^ ((r >> 1) & 7);
+    pa[h] = A + (row0 + r) * g.lda + kbeg + 2 * c;
+  }
+  const double* pb[TL::B_PW];
+#pragma unroll
+  for (int h = 0; h < TL::B_PW; ++h) {
+    const int kr = wave + TL::NW * h;
+    pb[h] = B + (kbeg + kr) * g.ldb + col0 + 2 * lane;
+  }
+  auto issue = [&](int64_t kt, int st) {
+    double* sa = lds + st * TL::STAGE;
+    double* sb = sa + TL::A_STAGE;
+#pragma unroll
+    for (int h = 0; h < TL::A_PW; ++h)
+      __builtin_amdgcn_global_load_lds((const void*)(pa[h] + kt * BK),
+                                       (lds_ptr)(sa + (wave + TL::NW * h) * 128), 16, 0, 0);
+#pragma unroll
+    for (int h = 0; h < TL::B_PW; ++h)
+      __builtin_amdgcn_global_load_lds((const void*)(pb[h] + kt * BK * g.ldb),
+                                       (lds_ptr)(sb + (wave + TL::NW * h) * TL::LDB), 16, 0, 0);
+  };
+
+  d4 acc[TL::MI][TL::NI];
+#pragma unroll
+  for (int i = 0; i < TL::MI; ++i)
+#pragma unroll
+    for (int j = 0; j < TL::NI; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  // rounds 0 .. NS - 2 in flight; round 0 landed when at most the later
+  // ones are outstanding (loads complete in issue order)
+  for (int r = 0; r < NS - 1; ++r)
+    if (r < nk) issue(r, r);
+  if (nk >= NS - 1)
+    __builtin_amdgcn_s_waitcnt(vm_wait((NS - 2) * TL::PW));
+  else
+    __builtin_amdgcn_s_waitcnt(0);
+  lds_barrier();
+  int st = 0;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    // the stage round kt + NS - 1 fills was read in round kt - 1, which
+    // every wave finished before the barrier that closed it
+    const bool ahead = kt + NS - 1 < nk;
+    if (ahead) issue(kt + NS - 1, st == 0 ? NS - 1 : st - 1);
+    const double* as = lds + st * TL::STAGE;
+    const double* bs = as + TL::A_STAGE;
+    __builtin_amdgcn_s_setprio(1);
+    d4 af[TL::MI];
+    double bf[TL::NI][4];
+#pragma unroll
+    for (int i = 0; i < TL::MI; ++i) {
+      const int r = wm * TL::WTM + i * 16 + lr;
+      const int sw = (r >> 1) & 7;
+      const d2 lo = *reinterpret_cast<const d2*>(as + r * 16 + ((2 * lg) ^ sw) * 2);
+      const d2 hi = *reinterpret_cast<const d2*>(as + r * 16 + ((2 * lg + 1) ^ sw) * 2);
+      af[i] = d4{lo.x, lo.y, hi.x, hi.y};
+    }
+#pragma unroll
+    for (int j = 0; j < TL::NI; ++j)
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+        bf[j][s4] = bs[(lg * 4 + s4) * TL::LDB + wn * TL::WTN + j * 16 + lr];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+      for (int i = 0; i < TL::MI; ++i)
+#pragma unroll
+        for (int j = 0; j < TL::NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s4], bf[j][s4], acc[i][j], 0, 0, 0);
+    __builtin_amdgcn_s_setprio(0);
+    // round kt + 1 must have landed before the barrier that opens it
+    if (ahead)
+      __builtin_amdgcn_s_waitcnt(vm_wait((NS - 2) * TL::PW));
+    else
+      __builtin_amdgcn_s_waitcnt(0);
+    lds_barrier();
+    st = st == NS - 1 ? 0 : st + 1;
+  }
+
+  // epilogue as gemm_f64_kernel's (full tile: no bounds checks needed, kept
+  // for the split case's shared form)
+  if (g.splits == 1) {
+    double* __restrict__ C = static_cast<double*>(g.C);
+    const double alpha = g.alpha, beta = g.beta;
+#pragma unroll
+    for (int i = 0; i < TL::MI; ++i)
+#pragma unroll
+      for (int j = 0; j < TL::NI; ++j) {
+        const int64_t col = col0 + wn * TL::WTN + j * 16 + lr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = row0 + wm * TL::WTM + i * 16 + v * 4 + lg;
+          double* p = C + row * g.ldc + col;
+          const double r = alpha * acc[i][j][v];
+          *p = beta != 0.0 ? r + beta * *p : r;
+        }
+      }
+  } else {
+    double* __restrict__ P = static_cast<double*>(g.P) + ic.split * g.split_stride;
+#pragma unroll
+    for (int i = 0; i < TL::MI; ++i)
+#pragma unroll
+      for (int j = 0; j < TL::NI; ++j) {
+        const int64_t col = col0 + wn * TL::WTN + j * 16 + lr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = row0 + wm * TL::WTM + i * 16 + v * 4 + lg;
+          P[row * g.ldp + col] = acc[i][j][v];
+        }
+      }
+  }
 }
 
 // WPE: waves per SIMD the register allocation must allow (the tile menu's
@@ -374,11 +559,21 @@ unsigned elementwise_blocks(int64_t total) {
   return (unsigned)b;
 }
 
-template <int BM, int BN, int BK, int WM, int WN, int WPE>
+// The DMA-staged form applies to full tiles with 16-byte aligned rows and
+// whole 16-k rounds in every split (NS = 0: no such form for the tile).
+template <int BM, int BN, int BK, int WM, int WN, int WPE, int NS>
 hipError_t launch_f64(const GemmArgs& g, hipStream_t s) {
   const int64_t items = g.tiles_m * g.tiles_n * g.splits;
   if (items <= 0) return hipSuccess;
   if (items > 0x7fffffffLL) return hipErrorInvalidValue;
+  if constexpr (NS > 0) {
+    if (g.m % BM == 0 && g.n % BN == 0 && g.vec_a && g.vec_b && g.k % BK == 0 &&
+        g.k_split % BK == 0 && g.k > 0) {
+      hipLaunchKernelGGL((gemm_f64_dma_kernel<BM, BN, WM, WN, NS, WPE>), dim3((unsigned)items),
+                         dim3(WM * WN * 64), 0, s, g);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK, WM, WN, WPE>), dim3((unsigned)items),
                      dim3(WM * WN * 64), 0, s, g);
   return hipGetLastError();
@@ -388,9 +583,9 @@ hipError_t launch_f64(const GemmArgs& g, hipStream_t s) {
 
 hipError_t launch_gemm_f64(int tile_id, const GemmArgs& g, hipStream_t s) {
   switch (tile_id) {
-    case 0: return launch_f64<128, 128, 16, 4, 2, 4>(g, s);
-    case 1: return launch_f64<64, 64, 16, 2, 2, 4>(g, s);
-    case 2: return launch_f64<256, 128, 16, 4, 4, 4>(g, s);
+    case 0: return launch_f64<128, 128, 16, 4, 2, 4, 2>(g, s);
+    case 1: return launch_f64<64, 64, 16, 2, 2, 4, 0>(g, s);
+    case 2: return launch_f64<256, 128, 16, 4, 4, 4, 3>(g, s);
     default: return hipErrorInvalidValue;
   }
 }

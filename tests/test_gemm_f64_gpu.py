@@ -177,3 +177,34 @@ def test_errors_do_not_launch(gpu):
     # inconsistent plans are rejected
     plan.p_k = 3
     assert cm.cosma_gemm_planned(plan, 1.0, A2, 4096, B2, 300, 0.0, C2, 300) == cm.COSMA_ERR_INVALID_ARG
+
+
+# Full tiles with 16-byte aligned rows and whole 16-k rounds run the
+# DMA-staged kernel form (tiles 0 and 2); a product one row taller runs the
+# register-staged form on every tile.  Both take each entry's k sum in the
+# same order, so the shared rows must agree bit for bit, and the aligned
+# product must meet the oracle's bound.
+@pytest.mark.parametrize("tile,pk", [(0, 1), (0, 3), (2, 1), (2, 2)])
+def test_dma_form_bit_equal_to_register_form(gpu, tile, pk):
+    import torch
+    rc, (bm, bn, _) = cm.cosma_tile_shape(F64, tile)
+    assert rc == 0
+    m, n, k = 2 * bm, 2 * bn, 16 * 37
+    log(f"f64 dma vs register form tile {tile} p_k {pk} {m}x{n}x{k}")
+    _, Ap = device_matrix(m + 1, k, 7, synth.STREAM_A, synth.UNIFORM_F64)
+    _, B = device_matrix(k, n, 7, synth.STREAM_B, synth.UNIFORM_F64)
+    C1 = torch.full((m, n), float("nan"), dtype=torch.float64, device="cuda")
+    C2 = torch.full((m + 1, n), float("nan"), dtype=torch.float64, device="cuda")
+    rc, plan = cm.cosma_plan_make(m, n, k, F64, tile, pk)
+    assert rc == 0 and plan.p_k == pk
+    assert run(m, n, k, Ap, k, B, n, C1, n, alpha=0.75, plan=plan) == 0
+    rc, plan2 = cm.cosma_plan_make(m + 1, n, k, F64, tile, pk)
+    assert rc == 0 and plan2.k_split == plan.k_split
+    assert run(m + 1, n, k, Ap, k, B, n, C2, n, alpha=0.75, plan=plan2) == 0
+    assert torch.equal(C1, C2[:m]), "DMA and register forms differ"
+    Ah = synth.gen(m + 1, k, 7, synth.STREAM_A, synth.UNIFORM_F64)[:m]
+    Bh = synth.gen(k, n, 7, synth.STREAM_B, synth.UNIFORM_F64)
+    ref, D = oracle.gemm(Ah, Bh, alpha=0.75)
+    err = oracle.normalised_err(C1.cpu().numpy(), ref, D)
+    log(f"  err={err:.3e} bound={oracle.fp64_bound(k):.3e}")
+    assert err <= oracle.fp64_bound(k)

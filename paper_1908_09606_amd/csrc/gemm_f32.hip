@@ -17,8 +17,9 @@
 // block), double-buffered as in section 7.3.  For BF16x3 a split pass
 // first writes A and B once as bf16 hi / lo planes in the order the GEMM
 // stages them (32-wide k blocks of padded rows, zero padding), so the GEMM
-// moves contiguous 16-byte chunks straight into the swizzled LDS layout
-// with no conversion arithmetic and no bounds checks in its main loop.
+// moves contiguous 16-byte chunks straight into LDS, already in the
+// matrix-core operand order, with no conversion arithmetic and no bounds
+// checks in its main loop.
 //
 // Matrix-core layouts (lane l, r = l % 16, g = l / 16, c = l % 32, q = l / 32):
 //   f32 16x16x4:  a = A[r][g], b = B[g][r], acc[v] = D[4g + v][r]
@@ -335,14 +336,11 @@ __global__ __launch_bounds__(WM* WN * 64) __attribute__((amdgpu_waves_per_eu(WPE
 }
 
 // ------------------------------------------------------------- BF16x3
-// LDS holds four planes per stage, all k-contiguous: A_hi, A_lo as [row][k]
-// and B_hi, B_lo as [col][k], rows of 32 bf16 (64 bytes) whose four 16-byte
-// chunks are XOR-swizzled (chunk c of row r at c ^ ((r ^ (r >> 2)) & 3)), so
-// every MFMA operand (8 consecutive k of one row / column) is one 16-byte
-// read and both these reads and the staging writes hit distinct bank quads.
-// Each thread stages 8 consecutive k of one A row (two 16-byte loads) and 8
-// consecutive k of one B column (eight 4-byte loads, coalesced across the
-// lanes of a wave, which cover consecutive columns).
+// LDS holds four planes per stage: A_hi, A_lo by rows and B_hi, B_lo by
+// columns, each round's 32 k of 16 rows (columns) as one 1 KiB group in
+// matrix-core operand order (the 16 bytes of k 8g .. 8g + 7 of row r at
+// position 16 g + r), so every MFMA operand is one 16-byte read per lane and
+// a wave's read of an operand is one 1 KiB group in lane order.
 template <int BM, int BN, int BK, int WM, int WN>
 struct X3Tile {
   static constexpr int NT = WM * WN * 64;
@@ -353,20 +351,19 @@ struct X3Tile {
   static constexpr int B_CHUNKS = BK * BN / 8 / NT;
   static constexpr int A_PLANE = BM * LD, B_PLANE = BN * LD;
   static constexpr int STAGE = 2 * A_PLANE + 2 * B_PLANE;  // bf16 elements
-  static_assert(BK == 32, "the LDS swizzle assumes 64-byte rows");
+  static_assert(BK == 32, "the operand order assumes 32 k per round");
   static_assert((BM * BK / 8) % NT == 0 && (BK * BN / 8) % NT == 0, "tiling");
   static_assert(2 * STAGE * 2 <= 160 * 1024, "LDS budget");
 };
 
-// Position of 16-byte chunk `chunk` (k % 32 in [8 chunk, 8 chunk + 8)) inside
-// the 64-byte row `row` of a plane, and the offset (in bf16) of that chunk in
-// a staged block whose rows start at a multiple of 16 (the swizzle depends on
-// the row modulo 16 only, so planes and LDS blocks share it).
-__device__ __forceinline__ int x3_chunk(int64_t row, int chunk) {
-  return (int)((chunk ^ row ^ (row >> 2)) & 3);
-}
-__device__ __forceinline__ int x3_off(int row, int chunk) {
-  return row * 32 + x3_chunk(row, chunk) * 8;
+// Offset (in bf16) of 16-byte chunk `chunk` (k % 32 in [8 chunk,
+// 8 chunk + 8)) of row `row` inside a round's block of a plane: rows come in
+// groups of 16 (512 bf16 = 1 KiB each), and within a group the chunk-th 16
+// bytes of row r sit at position 16 chunk + r.  That is the operand order of
+// v_mfma_f32_16x16x32_bf16 (lane 16 g + r takes k 8g .. 8g + 7 of row r), so
+// a wave's read of one 16-row operand is the 1 KiB group in lane order.
+__device__ __forceinline__ int64_t x3_pos(int64_t row, int chunk) {
+  return (row & ~(int64_t)15) * 32 + chunk * 128 + (row & 15) * 8;
 }
 
 // Round-to-nearest-even split of 8 floats into bf16 hi and lo pieces.
@@ -383,11 +380,12 @@ __device__ __forceinline__ void split8(const float (&x)[8], us8& hi, us8& lo) {
 
 // Split pass: FP32 operands -> bf16 hi / lo planes in the GEMM's staging
 // order.  A plane: element (row, k) at
-//   ((k / 32) * rows_p + row) * 32 + x3_chunk(row, (k % 32) / 8) * 8 + k % 8
+//   (k / 32) * rows_p * 32 + x3_pos(row, (k % 32) / 8) + k % 8
 // (rows_p = rows padded to 256, the tallest tile); B planes are stored
-// transposed, (col, k) likewise with cols_p (columns padded to 256).  Padding rows, columns and k hold zeros, so a tile's
-// round of any tile shape is one contiguous block, already in the swizzled
-// layout the GEMM's LDS uses, and the GEMM copies it with no bounds checks.
+// transposed, (col, k) likewise with cols_p (columns padded to 256).  Padding
+// rows, columns and k hold zeros, so a tile's round of any tile shape is one
+// contiguous block, already in the operand order the GEMM's LDS uses, and
+// the GEMM copies it with no bounds checks.
 constexpr int X3_K = 32;
 
 // A: one block per 16 rows x 256 k (8 rounds).  The FP32 values are read as
@@ -440,7 +438,7 @@ __global__ __launch_bounds__(256) void x3_split_a_kernel(const float* __restrict
       us8 hv, lv;
       split8(x, hv, lv);
       const int64_t row = row0 + r;
-      const int64_t off = (round * rows_p + row) * X3_K + x3_chunk(row, kc) * 8;
+      const int64_t off = round * rows_p * X3_K + x3_pos(row, kc);
       *reinterpret_cast<us8*>(hi + off) = hv;
       *reinterpret_cast<us8*>(lo + off) = lv;
     }
@@ -495,7 +493,7 @@ __global__ __launch_bounds__(256) void x3_split_b_kernel(const float* __restrict
     us8 hv, lv;
     split8(x, hv, lv);
     const int64_t col = col0 + cc;
-    const int64_t off = (round * cols_p + col) * X3_K + x3_chunk(col, kc) * 8;
+    const int64_t off = round * cols_p * X3_K + x3_pos(col, kc);
     *reinterpret_cast<us8*>(hi + off) = hv;
     *reinterpret_cast<us8*>(lo + off) = lv;
   }
@@ -503,7 +501,7 @@ __global__ __launch_bounds__(256) void x3_split_b_kernel(const float* __restrict
 
 // GEMM on the split planes.  A round's A_hi, A_lo (BM rows x 64 bytes each)
 // and B_hi, B_lo (BN columns x 64 bytes) blocks are contiguous and already
-// swizzled, so staging is a copy of 1 KiB pieces by 16-byte global-to-LDS
+// in operand order, so staging is a copy of 1 KiB pieces by 16-byte global-to-LDS
 // DMA (no registers, no LDS write instructions).  NS LDS stages form a ring:
 // the DMA of round r + NS - 1 is issued at the start of round r.
 typedef __attribute__((address_space(3))) void* lds_ptr;
@@ -565,7 +563,7 @@ __global__ __launch_bounds__(WM* WN * 64) void gemm_bf16x3_kernel(X3Args g) {
                                        0);
     }
   };
-  const int frag = x3_off(lr, lg);
+  const int frag = lane * 8;  // operand order: lane l reads the l-th 16 bytes of a group
   auto compute = [&](const unsigned short* st) {
     const unsigned short* a_hi = st;
     const unsigned short* a_lo = st + TL::A_PLANE;

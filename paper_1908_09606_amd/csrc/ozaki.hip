@@ -307,18 +307,15 @@ __global__ __launch_bounds__(oz_waves<S>() * 64) void ozaki_gemm_kernel(OzArgs g
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   // round kt computes from LDS stage kt % 2 while round kt + 1 fills the
-  // other stage and bn; the DMA writes must have landed before the barrier
-  // that opens the next round
+  // other stage and bn (issued between the products of slice 0); the DMA
+  // writes must have landed before the barrier that opens the next round
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int st = (int)(kt & 1);
 #pragma unroll
     for (int v = 0; v < S; ++v)
 #pragma unroll
       for (int j = 0; j < NJ; ++j) bc[v][j] = bn[v][j];
-    if (kt + 1 < nk) {
-      stage_a(kt + 1, st ^ 1);
-      load_b(kt + 1);
-    }
+    const bool more = kt + 1 < nk;
     // A fragments of slice u + 1 are read while the products of slice u
     // run: issued after its first two products, so that the wait before
     // those covers only fragments already needed
@@ -326,10 +323,39 @@ __global__ __launch_bounds__(oz_waves<S>() * 64) void ozaki_gemm_kernel(OzArgs g
     i4 afr[2][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) afr[0][i] = *reinterpret_cast<const i4*>(a_frag + i * 1024);
+    // the next round's loads (A_FRAGS / OZ_WAVES DMA fragments, S * NJ B
+    // fragments) go out one by one between the products of slice 0 (load t
+    // before product q with q LOADS <= t Q0 < (q + 1) LOADS), so the wave's
+    // matrix unit keeps working while it issues them.  (Written out here
+    // rather than through a helper: that form compiled to a rolled slice
+    // loop with its register arrays in scratch memory.)
+    constexpr int A_PW = A_FRAGS / OZ_WAVES, LOADS = A_PW + S * NJ, Q0 = S * 4 * NJ;
 #pragma unroll
     for (int u = 0; u < S; ++u) {
 #pragma unroll
       for (int q = 0; q < (S - u) * 4 * NJ; ++q) {
+        if (u == 0) {
+          const int t = q * LOADS / Q0;  // loads t .. of this gap
+#pragma unroll
+          for (int tt = t; tt < LOADS && tt * Q0 < (q + 1) * LOADS; ++tt) {
+            if (tt * Q0 < q * LOADS) continue;
+            __builtin_amdgcn_sched_barrier(0);
+            if (more) {
+              if (tt < A_PW) {
+                const int qq = wave + OZ_WAVES * tt;
+                const int uu = qq / (A_BLK / 1024), fr = qq % (A_BLK / 1024);
+                __builtin_amdgcn_global_load_lds(
+                    (const void*)(a_src + uu * a_plane + (kt + 1) * A_BLK + fr * 1024),
+                    (lds_ptr)(lds + (st ^ 1) * STAGE + uu * A_BLK + fr * 1024), 16, 0, 0);
+              } else {
+                const int v = (tt - A_PW) / NJ, j = (tt - A_PW) % NJ;
+                bn[v][j] =
+                    *reinterpret_cast<const i4*>(b_src + v * b_plane + (kt + 1) * B_BLK + j * 1024);
+              }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
         if (q == 2 && u + 1 < S) {
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll

@@ -259,12 +259,14 @@ COSMA_API int cosma_pgemm(int transa, int transb, int64_t m, int64_t n, int64_t 
    parallel" over many small problems) ------------------------------------ */
 
 /* Variable-size batch: problem i is C_i = alpha_i*A_i*B_i + beta_i*C_i.
-   Every problem gets a tile and a split factor p_k from the planner's batch
-   model: a problem whose work items would be long against the batch's
-   share per resident workgroup is cut in k (section 6.2's rule that k is
-   cut once processors outnumber independent (i, j) domains), its partials
-   reduced in ascending split order.  The problems run as one persistent
-   launch per tile variant (the problems must not alias each other's C).
+   The planner's batch model picks one tile for the whole batch (among the
+   tiles with a persistent form, the one whose modelled item costs sum
+   lowest) and a split factor p_k per problem: a problem whose work items
+   would be long against the batch's share per resident workgroup is cut in
+   k (section 6.2's rule that k is cut once processors outnumber independent
+   (i, j) domains), its partials reduced in ascending split order.  The
+   problems run as one persistent launch (the problems must not alias each
+   other's C).
    Supported dtypes: COSMA_F32, COSMA_F64 (else COSMA_ERR_UNSUPPORTED).
    All host arrays have length `count` and are read during the call only.
    The problem descriptors, the item map, the launch counters and the split
@@ -296,7 +298,7 @@ COSMA_API int cosma_workspace_size_batched(int64_t count, const int64_t* m, cons
    by class of problems (m n and k each binned by factors of four, the
    eight classes with the most flops first) it tries the other tiles and
    twice / half the current split factors, keeping a change that is more
-   than 1 % faster.  Otherwise the planner's batch model decides. */
+   than 1 % faster.  Otherwise policy 5 (as for cosma_gemm_batched). */
 COSMA_API int cosma_batch_create(int64_t count, const int64_t* m, const int64_t* n, const int64_t* k,
                        const double* alpha, const void* const* A, const int64_t* lda,
                        const void* const* B, const int64_t* ldb, const double* beta,
@@ -311,10 +313,11 @@ COSMA_API int cosma_batch_run(void* handle, void* stream);
 COSMA_API int cosma_batch_destroy(void* handle);
 /* Policy the autotuner started its refinement from (0 = the planner's batch model per problem,
    1 = all 64x64, 2 = all 128x128, 3 = size threshold, each with the model's
-   splits; 4 = the model's tiles with k never cut), number of persistent
-   launches (one per tile variant), work items, and the timed milliseconds
-   of each candidate policy (0 when tuning was skipped: some beta != 0, or
-   COSMA_AUTOTUNE=0). */
+   splits; 4 = the model's tiles with k never cut; 5 = one tile for the
+   whole batch, the lowest summed model cost, with the model's splits: the
+   policy used without tuning), number of persistent launches (one per tile
+   variant), work items, and the timed milliseconds of each candidate policy
+   (0 when tuning was skipped: some beta != 0, or COSMA_AUTOTUNE=0). */
 COSMA_API int cosma_batch_info(void* handle, int* policy, int* groups, int64_t* items,
                                double* policy_ms, int policy_ms_len);
 /* The autotuner's refinement: trials timed after the policies, the fastest

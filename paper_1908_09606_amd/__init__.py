@@ -282,7 +282,8 @@ def cosma_batch_destroy(handle) -> int:
     return lib().cosma_batch_destroy(handle)
 
 
-BATCH_POLICIES = 5
+BATCH_POLICIES = 6
+BATCH_POLICY_DEFAULT = 5  # one tile for the whole batch; what the one-shot call and an untuned handle use
 
 
 def cosma_batch_info(handle):

@@ -58,8 +58,13 @@ enum Policy {
   POLICY_ALL_128 = 2,    // every problem on 128 x 128, splits by the model
   POLICY_THRESHOLD = 3,  // 128 x 128 from m n >= 2^20, else 64 x 64, splits by the model
   POLICY_NO_SPLIT = 4,   // the model's tiles, k never cut
-  kPolicies = 5
+  POLICY_ONE_TILE = 5,   // one tile for the whole batch: the lowest summed model cost, model splits
+  kPolicies = 6
 };
+// What the one-shot call and an untuned handle use: one persistent launch
+// (tile groups run one after another on a stream, so several groups pay
+// several launch tails), on the tile whose modelled item costs sum lowest.
+constexpr int kDefaultPolicy = POLICY_ONE_TILE;
 
 // A problem as given, before a policy is applied.
 struct Input {
@@ -175,6 +180,23 @@ Assignment seed_assignment(const std::vector<Input>& in, int dtype, int policy,
   Assignment a;
   a.tile.resize(in.size());
   a.split.assign(in.size(), policy == POLICY_NO_SPLIT ? 1 : 0);
+  if (policy == POLICY_ONE_TILE) {
+    int cnt = 0;
+    tile_menu(dtype, &cnt);
+    int best = 0;
+    double best_t = INFINITY;
+    for (int id = 0; id < cnt; ++id) {
+      if (!batched_form(dtype, id)) continue;
+      double t = 0.0;
+      for (const Input& q : in) t += batch_item_cost(q.p.m, q.p.n, q.p.k, dtype, id, f);
+      if (t < best_t) {
+        best_t = t;
+        best = id;
+      }
+    }
+    a.tile.assign(in.size(), best);
+    return a;
+  }
   for (size_t i = 0; i < in.size(); ++i) a.tile[i] = policy_tile(policy, dtype, in[i].p, f);
   return a;
 }
@@ -429,7 +451,7 @@ int collect(int64_t count, const int64_t* m, const int64_t* n, const int64_t* k,
 
 struct Batch {
   int dtype = F32;
-  int policy = POLICY_MODEL;
+  int policy = kDefaultPolicy;
   double policy_ms[kPolicies] = {0};
   int trials = 0;         // refinement trials the autotuner timed
   double seed_ms = 0.0;   // best policy's time
@@ -685,7 +707,7 @@ int cosma_batch_create(int64_t count, const int64_t* m, const int64_t* n, const 
       bool all_beta_zero = true;
       for (const Input& q : b->inputs) all_beta_zero = all_beta_zero && q.p.beta == 0.0;
       for (const Scale& s : b->scales) all_beta_zero = all_beta_zero && s.beta == 0.0;
-      Assignment best = seed_assignment(b->inputs, dtype, POLICY_MODEL, f);
+      Assignment best = seed_assignment(b->inputs, dtype, kDefaultPolicy, f);
       if (autotune_enabled() && all_beta_zero && !b->inputs.empty())
         rc = autotune(*b, f, (hipStream_t)stream, best);
       if (rc == COSMA_OK) rc = materialise(*b, best, f);
@@ -782,7 +804,7 @@ int cosma_workspace_size_batched(int64_t count, const int64_t* m, const int64_t*
   int st = COSMA_OK;
   const cosma_device_facts f = device_facts(&st);
   Layout L;
-  build_layout(in, dtype, seed_assignment(in, dtype, POLICY_MODEL, f), f, L);
+  build_layout(in, dtype, seed_assignment(in, dtype, kDefaultPolicy, f), f, L);
   *bytes = in.empty() ? 0 : parts_of(L).total;
   return COSMA_OK;
 }
@@ -803,7 +825,7 @@ int cosma_gemm_batched(int64_t count, const int64_t* m, const int64_t* n, const 
   if (st != COSMA_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   Layout L;
-  build_layout(in, dtype, seed_assignment(in, dtype, POLICY_MODEL, f), f, L);
+  build_layout(in, dtype, seed_assignment(in, dtype, kDefaultPolicy, f), f, L);
   Placed pl{nullptr, nullptr, nullptr, nullptr};
   if (!L.probs.empty()) {
     void* ws = nullptr;

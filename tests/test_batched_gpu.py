@@ -128,7 +128,7 @@ def test_graph_handle_beta_nonzero_against_oracle(gpu):
     rc, h = cm.cosma_batch_create(*a, cm.COSMA_F64)
     assert rc == 0
     rc, policy, groups, items, ms = cm.cosma_batch_info(h)
-    assert policy == 0 and ms == [0.0] * cm.BATCH_POLICIES  # no tuning when some beta != 0
+    assert policy == cm.BATCH_POLICY_DEFAULT and ms == [0.0] * cm.BATCH_POLICIES  # no tuning when some beta != 0
     assert cm.cosma_batch_run(h) == 0
     torch.cuda.synchronize()
     for i, (m, n, k) in enumerate(dims):
@@ -224,7 +224,7 @@ def model_plan(dims, mats, dtype):
     rc, h = cm.cosma_batch_create(*a, dtype)
     assert rc == 0
     try:
-        assert cm.cosma_batch_info(h)[1] == 0
+        assert cm.cosma_batch_info(h)[1] == cm.BATCH_POLICY_DEFAULT
         rc, tiles = cm.cosma_batch_tiles(h, len(dims))
         rc2, splits = cm.cosma_batch_splits(h, len(dims))
         assert rc == 0 and rc2 == 0

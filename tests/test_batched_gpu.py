@@ -70,6 +70,11 @@ def test_graph_handle_bit_equal_to_single_launches(gpu, dtype, dist):
     try:
         rc, policy, groups, items, ms = cm.cosma_batch_info(h)
         log(f"batch policy {policy} groups {groups} items {items} tuned ms {ms}")
+        # the refinement starts from the fastest policy and keeps only gains
+        rc, trials, seed_ms, tuned_ms = cm.cosma_batch_tuning(h)
+        log(f"  refinement: {trials} trials, {seed_ms:.4f} -> {tuned_ms:.4f} ms")
+        assert rc == 0 and trials >= 0
+        assert seed_ms == min(ms) and ms[policy] == seed_ms and 0.0 < tuned_ms <= seed_ms
         rc, tiles = cm.cosma_batch_tiles(h, len(dims))
         assert rc == 0 and all(t >= 0 for t, d in zip(tiles, dims) if d[0] and d[1] and d[2])
         rc, splits = cm.cosma_batch_splits(h, len(dims))

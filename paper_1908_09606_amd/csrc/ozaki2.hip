@@ -32,6 +32,7 @@
 #include <climits>
 #include <cstring>
 
+#include "batch_device.hpp"
 #include "crt.hpp"
 #include "kernels.hpp"
 #include "ozaki.hpp"
@@ -105,19 +106,31 @@ __global__ __launch_bounds__(256) void residue_a_kernel(const double* __restrict
   const int64_t rounds = kp / O2_BK;
   const int64_t rb = blockIdx.x / rounds, R = blockIdx.x % rounds;
   const int t = threadIdx.x;
-  for (int c = t; c < 64 * O2_BK; c += 256) {
-    const int r = c >> 6, kk = c & 63;
-    const int64_t row = rb * 64 + r, kt = R * O2_BK + kk;
-    // A row marked non-finite has e = OZAKI_NONFINITE: the shift then takes
-    // its finite entries to zero and leaves NaN / infinity, which the
-    // magnitude test zeroes (finite rows stay below 2^50).  Testing the
-    // value rather than the marker keeps the load independent of e[row].
-    double x = 0.0;
-    if (row < m && kt < k) {
-      x = rint(ldexp(A[row * lda + kt], cp.beta - e[row]));
-      x = fabs(x) <= 0x1p60 ? x : 0.0;
+  // Wave w reads rows w, w + 4, ..., w + 60 of the block, lane kk its k:
+  // 512 contiguous bytes per load, all 16 loads in flight at once (rows
+  // and k beyond the matrix read a valid entry and are replaced by zero).
+  {
+    const int kk = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int64_t kt = R * O2_BK + kk;
+    double a[16];
+    int ex[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int64_t row = rb * 64 + w + 4 * j;
+      const bool ok = row < m && kt < k;
+      a[j] = A[ok ? row * lda + kt : 0];
+      ex[j] = e[row < m ? row : 0];
     }
-    tile[r][kk] = x;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int64_t row = rb * 64 + w + 4 * j;
+      // A row marked non-finite has e = OZAKI_NONFINITE: the shift then
+      // takes its finite entries to zero and leaves NaN / infinity, which
+      // the magnitude test zeroes (finite rows stay below 2^50).
+      double x = rint(ldexp(a[j], cp.beta - ex[j]));
+      x = fabs(x) <= 0x1p60 ? x : 0.0;
+      tile[w + 4 * j][kk] = row < m && kt < k ? x : 0.0;
+    }
   }
   __syncthreads();
   const int lane = t & 63, w = t >> 6, g = lane >> 4, rr = lane & 15;
@@ -144,15 +157,25 @@ __global__ __launch_bounds__(256) void residue_b_kernel(const double* __restrict
   const int64_t rounds = kp / O2_BK;
   const int64_t cb = blockIdx.x / rounds, R = blockIdx.x % rounds;
   const int t = threadIdx.x;
-  for (int c = t; c < 64 * O2_BK; c += 256) {
-    const int kk = c >> 6, cc = c & 63;
-    const int64_t col = cb * 64 + cc, kt = R * O2_BK + kk;
-    double x = 0.0;
-    if (col < n && kt < k) {  // non-finite columns: as for the rows of A
-      x = rint(ldexp(B[kt * ldb + col], cp.beta - f[col]));
-      x = fabs(x) <= 0x1p60 ? x : 0.0;
+  // Wave w reads k rows w, w + 4, ..., w + 60 of the round, lane cc its
+  // column: 512 contiguous bytes per load, all 16 in flight at once.
+  {
+    const int cc = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int64_t col = cb * 64 + cc;
+    const int fc = f[col < n ? col : 0];
+    double b[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int64_t kt = R * O2_BK + w + 4 * j;
+      b[j] = B[col < n && kt < k ? kt * ldb + col : 0];
     }
-    tile[kk][cc] = x;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int64_t kt = R * O2_BK + w + 4 * j;
+      double x = rint(ldexp(b[j], cp.beta - fc));  // non-finite columns: as for A
+      x = fabs(x) <= 0x1p60 ? x : 0.0;
+      tile[w + 4 * j][cc] = col < n && kt < k ? x : 0.0;
+    }
   }
   __syncthreads();
   const int lane = t & 63, w = t >> 6, g = lane >> 4, rr = lane & 15;
@@ -340,51 +363,76 @@ struct CrtArgs {
 // exact, q = rint(X / M) < 2^22 and X - q M = C' is exact limb by limb.
 template <int NM, int L>
 __global__ __launch_bounds__(256) void crt_kernel(CrtArgs a) {
-  const int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x;  // dword index in a plane
-  if (d * 4 >= a.plane) return;
-  const int64_t tile = d >> 13;               // 8192 dwords per tile
-  const int w = (int)(d >> 10) & 7, blk = (int)(d >> 6) & 15, q = (int)d & 63;
+  // A tile's residues are 8192 dwords per outer index, 32 workgroups of 256
+  // threads; the tile and its base address are the same for the whole
+  // workgroup, so each load takes a scalar base and a 32-bit lane offset.
+  const int64_t tile = blockIdx.x >> 5;
+  const int dl = (int)(blockIdx.x & 31) * 256 + (int)threadIdx.x;  // dword in the tile
+  if (tile * 32768 + (int64_t)dl * 4 >= a.plane) return;
+  const int w = dl >> 10, blk = (dl >> 6) & 15, q = dl & 63;
   const int64_t row0 = (tile / a.tiles_n) * 256 + (w >> 1) * 64 + (blk >> 2) * 16 + (q >> 4) * 4;
   const int64_t col = (tile % a.tiles_n) * 128 + (w & 1) * 64 + (blk & 3) * 16 + (q & 15);
   if (row0 >= a.m || col >= a.n) return;
   const CrtParams& cp = a.cp;
-  const unsigned* y = reinterpret_cast<const unsigned*>(a.y) + d;
-  const int64_t pd = a.plane / 4;
-  // residues of the four rows, summed over the splits
-  unsigned sum[NM][4];
-  if (a.splits == 1) {
-    unsigned x[NM];
-#pragma unroll
-    for (int l = 0; l < NM; ++l) x[l] = y[l * pd];
-#pragma unroll
-    for (int l = 0; l < NM; ++l)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sum[l][v] = (x[l] >> (8 * v)) & 0xffu;
-  } else {
-#pragma unroll
-    for (int l = 0; l < NM; ++l) sum[l][0] = sum[l][1] = sum[l][2] = sum[l][3] = 0;
-    for (int64_t s = 0; s < a.splits; ++s) {
-#pragma unroll
-      for (int l = 0; l < NM; ++l) {
-        const unsigned x = y[(s * NM + l) * pd];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) sum[l][v] += (x >> (8 * v)) & 0xffu;
-      }
-    }
-  }
+  const int off = dl * 4;
+  // dword of this thread for outer index o: a buffer load over the tile's
+  // 32 KiB of that index (base in scalar registers, read through the first
+  // lane) at the lane's 32-bit offset, so no lane computes a 64-bit address
+  auto res = [&](int64_t o) {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)uniform_ptr(a.y + tile * 32768 + o * a.plane), 0, 32768, 0x00020000);
+    return (unsigned)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+  };
   double acc[4][L];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
     for (int i = 0; i < L; ++i) acc[v][i] = 0.0;
+  // acc[v] += r_l(v) T_l for every modulus.  The L limbs of T_l come from
+  // the kernel arguments through scalar registers, which cannot hold all
+  // NM * L of them at once: the products run modulus by modulus over all
+  // four rows; empty asm statements on the residues before and the
+  // accumulators after each modulus keep the compiler from regrouping the
+  // products row by row (which would keep every limb live to the end) or
+  // converting every residue up front.
+  auto accumulate = [&](auto residue) {
 #pragma unroll
-  for (int l = 0; l < NM; ++l)
+    for (int l = 0; l < NM; ++l) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const double r = (double)sum[l][v];
+      for (int v = 0; v < 4; ++v) {
+        unsigned rv = residue(l, v);
+        asm volatile("" : "+v"(rv));  // converted here, not all up front
+        const double r = (double)rv;
 #pragma unroll
-      for (int i = 0; i < L; ++i) acc[v][i] = fma(r, cp.t[l][i], acc[v][i]);
+        for (int i = 0; i < L; ++i) acc[v][i] = fma(r, cp.t[l][i], acc[v][i]);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int i = 0; i < L; ++i) asm volatile("" : "+v"(acc[v][i]));
     }
+  };
+  if (a.splits == 1) {
+    // one dword per modulus, its bytes taken as the products need them
+    unsigned x[NM];
+#pragma unroll
+    for (int l = 0; l < NM; ++l) x[l] = res(l);
+    accumulate([&](int l, int v) { return (x[l] >> (8 * v)) & 0xffu; });
+  } else {
+    // residues of the four rows, summed over the splits
+    unsigned sum[NM][4];
+#pragma unroll
+    for (int l = 0; l < NM; ++l) sum[l][0] = sum[l][1] = sum[l][2] = sum[l][3] = 0;
+    for (int64_t s = 0; s < a.splits; ++s) {
+#pragma unroll
+      for (int l = 0; l < NM; ++l) {
+        const unsigned x = res(s * NM + l);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sum[l][v] += (x >> (8 * v)) & 0xffu;
+      }
+    }
+    accumulate([&](int l, int v) { return sum[l][v]; });
+  }
   const int fj = a.f[col];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {

@@ -54,8 +54,8 @@ __global__ __launch_bounds__(256) void row_exp_kernel(const double* __restrict__
   if (row >= m) return;
   double mx = 0.0;
   bool bad = false;
-#pragma unroll 8
-  for (int64_t t = lane; t < k; t += 64) {  // unrolled: eight loads in flight per lane
+#pragma unroll 16
+  for (int64_t t = lane; t < k; t += 64) {  // unrolled: 16 loads in flight per lane
     const double v = A[row * lda + t];
     bad |= !isfinite(v);
     mx = fmax(mx, fabs(v));
@@ -84,8 +84,8 @@ __global__ __launch_bounds__(256) void col_exp_kernel(const double* __restrict__
   const int64_t t1 = min64(k, t0 + COL_CHUNK);
   double mx = 0.0;
   bool bad = false;
-#pragma unroll 8
-  for (int64_t t = t0; t < t1; ++t) {  // unrolled: eight loads in flight per thread
+#pragma unroll 16
+  for (int64_t t = t0; t < t1; ++t) {  // unrolled: 16 loads in flight per thread
     const double v = B[t * ldb + col];
     bad |= !isfinite(v);
     mx = fmax(mx, fabs(v));
@@ -137,6 +137,37 @@ __device__ __forceinline__ int frag_offset(int rr, int g) {
   return (rr >> 4) * 1024 + (g * 16 + (rr & 15)) * 16;
 }
 
+// Stage of the A slicing passes: rows r0 .. r0 + 127, k0 .. k0 + 31 of A,
+// scaled by 2^-e[row], into tile.  Thread t takes k pair 2 (t % 16) of rows
+// t / 16 + 16 j: sixteen rows of 256 contiguous bytes per wave, all 16 loads
+// of a thread in flight at once (entries outside A read A[0] and become
+// zero).  The loads do not wait for the exponent: a row marked non-finite
+// is zeroed after them.
+template <int LD>
+__device__ __forceinline__ void slice_a_stage(const double* __restrict__ A, int64_t m, int64_t k,
+                                              int64_t lda, const int* __restrict__ e, int64_t r0,
+                                              int64_t k0, double (&tile)[128][LD]) {
+  const int kk = (threadIdx.x & 15) * 2, rq = threadIdx.x >> 4;
+  const bool ok0 = k0 + kk < k, ok1 = k0 + kk + 1 < k;
+  double a0[8], a1[8];
+  int ex[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int64_t row = r0 + rq + 16 * j;
+    const bool rok = row < m;
+    const int64_t at = row * lda + k0 + kk;
+    a0[j] = A[rok && ok0 ? at : 0];
+    a1[j] = A[rok && ok1 ? at + 1 : 0];
+    ex[j] = e[rok ? row : 0];
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const bool use = r0 + rq + 16 * j < m && ex[j] != OZAKI_NONFINITE;
+    tile[rq + 16 * j][kk] = use && ok0 ? ldexp(a0[j], -ex[j]) : 0.0;
+    tile[rq + 16 * j][kk + 1] = use && ok1 ? ldexp(a1[j], -ex[j]) : 0.0;
+  }
+}
+
 // A: one workgroup per (row tile, k round, half of the round): the 128 x 32
 // values are read in 16-byte pieces, eight rows of 256 contiguous bytes per
 // wave instruction, scaled and transposed through LDS (34 KiB, so that
@@ -155,24 +186,7 @@ __global__ __launch_bounds__(256) void slice_a_kernel(const double* __restrict__
   const int64_t blk = blockIdx.x >> 1;  // row_tile * rounds + round
   const int half = blockIdx.x & 1;
   const int64_t r0 = (blk / rounds) * OZ_BM, k0 = (blk % rounds) * OZ_BK + half * SA_K;
-  for (int c = threadIdx.x; c < OZ_BM * SA_K / 2; c += 256) {
-    const int r = c / (SA_K / 2), kk = (c % (SA_K / 2)) * 2;
-    const int64_t row = r0 + r;
-    // the loads do not wait for the exponent: a row marked non-finite is
-    // zeroed after them
-    double x0 = 0.0, x1 = 0.0;
-    if (row < m) {
-      const double a0 = k0 + kk < k ? A[row * lda + k0 + kk] : 0.0;
-      const double a1 = k0 + kk + 1 < k ? A[row * lda + k0 + kk + 1] : 0.0;
-      const int er = e[row];
-      if (er != OZAKI_NONFINITE) {
-        x0 = ldexp(a0, -er);
-        x1 = ldexp(a1, -er);
-      }
-    }
-    tile[r][kk] = x0;
-    tile[r][kk + 1] = x1;
-  }
+  slice_a_stage(A, m, k, lda, e, r0, k0, tile);
   __syncthreads();
   // 256 chunks of 16 values (128 rows x 2): one per thread
   const int c = threadIdx.x;
@@ -195,7 +209,11 @@ __global__ __launch_bounds__(256) void slice_b_kernel(const double* __restrict__
   const int64_t kc = (id / cols) * 16, col = id - (id / cols) * cols;
   double x[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) x[i] = (col < n && kc + i < k) ? B[(kc + i) * ldb + col] : 0.0;
+  for (int i = 0; i < 16; ++i) {  // entries outside B read B[0] and become zero
+    const bool ok = col < n && kc + i < k;
+    const double v = B[ok ? (kc + i) * ldb + col : 0];
+    x[i] = ok ? v : 0.0;
+  }
   // a column marked non-finite is zeroed after the loads (they do not wait
   // for the exponent)
   const int fc = col < n ? f[col] : 0;

@@ -114,23 +114,30 @@ __global__ __launch_bounds__(256) void slice_a_bf16_kernel(const double* __restr
   const int64_t rounds = kp / OB_BK;
   const int64_t blk = blockIdx.x;  // row_tile * rounds + round
   const int64_t r0 = (blk / rounds) * OB_BM, k0 = (blk % rounds) * OB_BK;
-  for (int c = threadIdx.x; c < OB_BM * OB_BK / 2; c += 256) {
-    const int r = c / (OB_BK / 2), kk = (c % (OB_BK / 2)) * 2;
-    const int64_t row = r0 + r;
-    // the loads do not wait for the exponent: a row marked non-finite is
-    // zeroed after them
-    double x0 = 0.0, x1 = 0.0;
-    if (row < m) {
-      const double a0 = k0 + kk < k ? A[row * lda + k0 + kk] : 0.0;
-      const double a1 = k0 + kk + 1 < k ? A[row * lda + k0 + kk + 1] : 0.0;
-      const int er = e[row];
-      if (er != OZAKI_NONFINITE) {
-        x0 = ldexp(a0, -er);
-        x1 = ldexp(a1, -er);
-      }
+  // rows r0 .. r0 + 127 and k0 .. k0 + 31, read as in the int8 slicing
+  // pass: thread t takes k pair 2 (t % 16) of rows t / 16 + 16 j, all 16
+  // loads in flight at once (entries outside A read A[0] and become zero;
+  // a row marked non-finite is zeroed after the loads)
+  {
+    const int kk = (threadIdx.x & 15) * 2, rq = threadIdx.x >> 4;
+    const bool ok0 = k0 + kk < k, ok1 = k0 + kk + 1 < k;
+    double a0[8], a1[8];
+    int ex[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t row = r0 + rq + 16 * j;
+      const bool rok = row < m;
+      const int64_t at = row * lda + k0 + kk;
+      a0[j] = A[rok && ok0 ? at : 0];
+      a1[j] = A[rok && ok1 ? at + 1 : 0];
+      ex[j] = e[rok ? row : 0];
     }
-    tile[r][kk] = x0;
-    tile[r][kk + 1] = x1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const bool use = r0 + rq + 16 * j < m && ex[j] != OZAKI_NONFINITE;
+      tile[rq + 16 * j][kk] = use && ok0 ? ldexp(a0[j], -ex[j]) : 0.0;
+      tile[rq + 16 * j][kk + 1] = use && ok1 ? ldexp(a1[j], -ex[j]) : 0.0;
+    }
   }
   __syncthreads();
   // 512 chunks of 8 values (128 rows x 4): two per thread
@@ -156,7 +163,11 @@ __global__ __launch_bounds__(256) void slice_b_bf16_kernel(const double* __restr
   const int64_t kc = (id / cols) * 8, col = id - (id / cols) * cols;
   double x[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) x[i] = (col < n && kc + i < k) ? B[(kc + i) * ldb + col] : 0.0;
+  for (int i = 0; i < 8; ++i) {  // entries outside B read B[0] and become zero
+    const bool ok = col < n && kc + i < k;
+    const double v = B[ok ? (kc + i) * ldb + col : 0];
+    x[i] = ok ? v : 0.0;
+  }
   // a column marked non-finite is zeroed after the loads (they do not wait
   // for the exponent)
   const int fc = col < n ? f[col] : 0;

@@ -10,6 +10,7 @@ There is no fallback: if the library is missing every call raises.
 """
 from __future__ import annotations
 
+import array
 import ctypes
 import os
 import threading
@@ -186,16 +187,38 @@ def _dtype(d) -> int:
     return DTYPES[d] if isinstance(d, str) else int(d)
 
 
+# Arrays for the batched calls are built through the array module (one C
+# conversion pass) and handed to ctypes without a copy; the ctypes object
+# keeps the array alive.
+def _carray(ctype, code, values):
+    if not values:
+        return (ctype * 0)()
+    a = array.array(code, values)
+    return (ctype * len(a)).from_buffer(a)
+
+
 def _i64arr(v):
-    return (ctypes.c_int64 * len(v))(*[int(x) for x in v])
+    v = list(v)
+    try:
+        return _carray(ctypes.c_int64, "q", v)
+    except TypeError:  # values that are not integers: converted one by one
+        return _carray(ctypes.c_int64, "q", [int(x) for x in v])
 
 
 def _dblarr(v):
-    return (ctypes.c_double * len(v))(*[float(x) for x in v])
+    v = list(v)
+    try:
+        return _carray(ctypes.c_double, "d", v)
+    except TypeError:
+        return _carray(ctypes.c_double, "d", [float(x) for x in v])
 
 
 def _ptrarr(v):
-    return (ctypes.c_void_p * len(v))(*[_ptr(x) for x in v])
+    v = list(v)
+    try:  # all tensors
+        return _carray(ctypes.c_void_p, "Q", [x.data_ptr() for x in v])
+    except AttributeError:
+        return _carray(ctypes.c_void_p, "Q", [_ptr(x) or 0 for x in v])
 
 
 # ------------------------------------------------------------ C names

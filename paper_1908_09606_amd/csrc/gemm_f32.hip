@@ -227,6 +227,11 @@ __device__ __forceinline__ void f32_tile_body(const GemmArgs& g, const ItemCoord
   constexpr int KS = BLK / 4;                  // k per lane group and 16-k group
   static_assert(KS % 4 == 0 && KS * (64 / BLK) == 16, "k split of a 16-k group");
   const bool a_in = row0 + BM <= g.m, b_in = col0 + BN <= g.n;
+  // On an edge tile a wave whose rows or columns all lie outside C skips
+  // its LDS reads and products (it still loads, stores and meets every
+  // barrier), leaving the matrix cores of its SIMD to the other waves.
+  const bool live = FAST || __builtin_amdgcn_readfirstlane(
+                                (int)(row0 + wm * TL::WTM < g.m && col0 + wn * TL::WTN < g.n));
 
   acc_t acc[TL::MI][TL::NI];
 #pragma unroll
@@ -251,7 +256,7 @@ __device__ __forceinline__ void f32_tile_body(const GemmArgs& g, const ItemCoord
     const float* as = As[cur];
     const float* bs = Bs[cur];
 #pragma unroll
-    for (int h = 0; h < BK / 16; ++h) {
+    for (int h = 0; h < (live ? BK / 16 : 0); ++h) {
       f4 af[TL::MI][KS / 4];
       float bf[TL::NI][KS];
 #pragma unroll

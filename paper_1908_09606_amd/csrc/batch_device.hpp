@@ -1,29 +1,16 @@
 // Device side of the persistent batched launches: the item a workgroup
-// takes and its problem's launch arguments, held in scalar registers.
+// takes and its problem's launch arguments, held in scalar registers (the
+// whole workgroup works on one item, so every such value is the same in all
+// lanes).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
 #include "tiles.hpp"
+#include "uniform.hpp"
 
 namespace cosma {
-
-// The whole workgroup works on one item, so every value below is the same
-// in all lanes; reading it through the first lane keeps it in scalar
-// registers instead of one vector register per lane.
-__device__ __forceinline__ int64_t uniform_i64(int64_t x) {
-  const int lo = __builtin_amdgcn_readfirstlane((int)x);
-  const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
-  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-template <class T>
-__device__ __forceinline__ T* uniform_ptr(T* p) {
-  return reinterpret_cast<T*>(uniform_i64(reinterpret_cast<int64_t>(p)));
-}
-__device__ __forceinline__ double uniform_f64(double x) {
-  return __builtin_bit_cast(double, uniform_i64(__builtin_bit_cast(int64_t, x)));
-}
 
 // The next item of a launch for the calling thread's workgroup (called by
 // one thread): the workgroup's own chunk first, then the following chunks

@@ -32,13 +32,13 @@
 #include <climits>
 #include <cstring>
 
-#include "batch_device.hpp"
 #include "crt.hpp"
 #include "kernels.hpp"
 #include "ozaki.hpp"
 #include "planner.hpp"
 #include "runtime.hpp"
 #include "tiles.hpp"
+#include "uniform.hpp"
 
 namespace cosma {
 namespace {

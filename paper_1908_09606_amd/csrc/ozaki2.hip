@@ -377,7 +377,9 @@ __global__ __launch_bounds__(256) void crt_kernel(CrtArgs a) {
   const int off = dl * 4;
   // dword of this thread for outer index o: a buffer load over the tile's
   // 32 KiB of that index (base in scalar registers, read through the first
-  // lane) at the lane's 32-bit offset, so no lane computes a 64-bit address
+  // lane) at the lane's 32-bit offset, so no lane computes a 64-bit address.
+  // Descriptor: stride 0 (raw bytes), 32768 bytes in range, and the third
+  // word's 32-bit data format that gfx9-family buffer loads expect.
   auto res = [&](int64_t o) {
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
         (void*)uniform_ptr(a.y + tile * 32768 + o * a.plane), 0, 32768, 0x00020000);

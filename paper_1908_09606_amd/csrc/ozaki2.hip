@@ -361,7 +361,7 @@ struct CrtArgs {
 // not reduced) is congruent to C' modulo M; in 30-bit limbs every limb sum
 // stays below 16 * 256 * splits * 2^30 < 2^53 (splits <= 1024), so X is
 // exact, q = rint(X / M) < 2^22 and X - q M = C' is exact limb by limb.
-template <int NM, int L>
+template <int NM, int L, bool SPLIT>
 __global__ __launch_bounds__(256) void crt_kernel(CrtArgs a) {
   // A tile's residues are 8192 dwords per outer index, 32 workgroups of 256
   // threads; the tile and its base address are the same for the whole
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(256) void crt_kernel(CrtArgs a) {
         for (int i = 0; i < L; ++i) asm volatile("" : "+v"(acc[v][i]));
     }
   };
-  if (a.splits == 1) {
+  if (!SPLIT) {  // one split: the launch's register count is that of this path alone
     // one dword per modulus, its bytes taken as the products need them
     unsigned x[NM];
 #pragma unroll
@@ -471,10 +471,18 @@ __global__ __launch_bounds__(256) void crt_kernel(CrtArgs a) {
 
 template <int NM>
 hipError_t launch_crt_nm(const CrtArgs& c, unsigned grid, hipStream_t s) {
-  if (c.cp.limbs <= 4)
-    hipLaunchKernelGGL((crt_kernel<NM, 4>), dim3(grid), dim3(256), 0, s, c);
-  else
-    hipLaunchKernelGGL((crt_kernel<NM, 5>), dim3(grid), dim3(256), 0, s, c);
+  const bool split = c.splits > 1;
+  if (c.cp.limbs <= 4) {
+    if (split)
+      hipLaunchKernelGGL((crt_kernel<NM, 4, true>), dim3(grid), dim3(256), 0, s, c);
+    else
+      hipLaunchKernelGGL((crt_kernel<NM, 4, false>), dim3(grid), dim3(256), 0, s, c);
+  } else {
+    if (split)
+      hipLaunchKernelGGL((crt_kernel<NM, 5, true>), dim3(grid), dim3(256), 0, s, c);
+    else
+      hipLaunchKernelGGL((crt_kernel<NM, 5, false>), dim3(grid), dim3(256), 0, s, c);
+  }
   return hipGetLastError();
 }
 

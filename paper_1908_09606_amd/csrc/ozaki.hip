@@ -138,11 +138,11 @@ __device__ __forceinline__ int frag_offset(int rr, int g) {
 }
 
 // Stage of the A slicing passes: rows r0 .. r0 + 127, k0 .. k0 + 31 of A,
-// scaled by 2^-e[row], into tile.  Thread t takes k pair 2 (t % 16) of rows
-// t / 16 + 16 j: sixteen rows of 256 contiguous bytes per wave, all 16 loads
-// of a thread in flight at once (entries outside A read A[0] and become
-// zero).  The loads do not wait for the exponent: a row marked non-finite
-// is zeroed after them.
+// scaled by 2^-e[row], into tile.  Thread t takes the k pair 2 (t % 16) of
+// rows t / 16 + 16 j (j < 8): each pair of loads of a wave covers 256
+// contiguous bytes of four rows, and all 16 loads of a thread are in flight
+// at once (entries outside A read A[0] and become zero).  The loads do not
+// wait for the exponent: a row marked non-finite is zeroed after them.
 template <int LD>
 __device__ __forceinline__ void slice_a_stage(const double* __restrict__ A, int64_t m, int64_t k,
                                               int64_t lda, const int* __restrict__ e, int64_t r0,
@@ -169,8 +169,8 @@ __device__ __forceinline__ void slice_a_stage(const double* __restrict__ A, int6
 }
 
 // A: one workgroup per (row tile, k round, half of the round): the 128 x 32
-// values are read in 16-byte pieces, eight rows of 256 contiguous bytes per
-// wave instruction, scaled and transposed through LDS (34 KiB, so that
+// values are read as described at slice_a_stage, scaled and transposed
+// through LDS (34 KiB, so that
 // several workgroups share a CU); then each of the 256 chunks of 16
 // consecutive k is digitised by one thread and its 16 digit bytes per slice
 // go to their fragment slot (chunks 2 h, 2 h + 1 of the round: a wave writes

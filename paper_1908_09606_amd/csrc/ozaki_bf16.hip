@@ -100,9 +100,9 @@ __device__ __forceinline__ int frag_offset(int rr, int g) {
   return (rr >> 4) * 1024 + (g * 16 + (rr & 15)) * 16;
 }
 
-// A: one workgroup per (row tile, k round): 128 x 32 values read as 16-byte
-// pieces (four rows of 256 contiguous bytes per wave instruction), scaled
-// and transposed through LDS; then each chunk of 8 consecutive k is
+// A: one workgroup per (row tile, k round): 128 x 32 values read in 8-byte
+// loads (each pair of loads of a wave covers 256 contiguous bytes of four
+// rows), scaled and transposed through LDS; then each chunk of 8 consecutive k is
 // digitised and its 16 bytes per slice go to their fragment slot (a wave's
 // 64 chunks fill one 1 KiB fragment).
 __global__ __launch_bounds__(256) void slice_a_bf16_kernel(const double* __restrict__ A, int64_t m,
